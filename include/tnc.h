@@ -1,0 +1,257 @@
+/*
+ * tnc -- sliced tensor-network amplitudes on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows the paper (Fu et al., "Achieving Energetic
+ * Superiority Through System-Level Quantum Circuit Simulation"):
+ *   - a sub-network is a list of initial tensors plus a contraction path given
+ *     as a sequence of pairwise einsums (Sec. 3.1, Alg. 1 "init");
+ *   - slicing fixes the values of chosen labels; every assignment is an
+ *     independent sub-network and the full result is the sum over all of them
+ *     (Sec. 3.1, three-level scheme, global level);
+ *   - the output is a set of bitstring amplitudes; bitstrings that share some
+ *     qubit values form a correlated subspace whose open qubits are computed
+ *     together (Sec. 1 and 2.3, correlated samples);
+ *   - each pairwise contraction is an index permutation followed by a GEMM
+ *     (Sec. 3.4.2), which is a pure GEMM exactly when the reduced labels are
+ *     the intersection of the two operands' labels (Sec. 3.3, Eqs.
+ *     contraction and remain_idx);
+ *   - complex-half storage multiplies through one real GEMM whose small
+ *     operand is padded to [B(re,-im), B(im,re)] (Sec. 3.3, Eq. eq_modified2).
+ *
+ * Conventions shared by every call:
+ *   - Every label has dimension 2.  A tensor of rank r has 2^r complex entries.
+ *   - Dense data is row-major with the first label slowest.
+ *   - A bitstring is a uint64 whose bit q is the value of qubit q.
+ *   - Return value: TNC_OK (0) or a negative TNC_E* code; tnc_last_error()
+ *     then returns a message (thread-local, valid until the next call on the
+ *     same thread).
+ *   - Handles are owned by the caller and released with the matching
+ *     *_destroy call.  A context and everything made from it is used from one
+ *     host thread at a time.
+ *   - Device pointers are HIP device addresses on the context's device; host
+ *     pointers are ordinary host memory.  Every pointer argument marked "host"
+ *     is read or written synchronously before the call returns.
+ */
+#ifndef TNC_H
+#define TNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TNC_OK = 0,
+    TNC_EINVAL = -1,       /* malformed argument (shape, label, path, range)      */
+    TNC_ENOMEM = -2,       /* per-slice working set exceeds the workspace          */
+    TNC_EDEVICE = -3,      /* a HIP runtime call failed                             */
+    TNC_EOVERFLOW = -4,    /* FP16 range exceeded after the bounded rescale replays */
+    TNC_EUNSUPPORTED = -5  /* valid input this engine does not handle               */
+};
+
+/* Arithmetic of the contraction steps.
+ *   C64     : complex64 storage, FP32 matrix-core GEMM (4M as one real GEMM).
+ *   F16_4M  : complex FP16 storage (re,im interleaved, 4 bytes per entry),
+ *             one real FP16 GEMM with the padded small operand, FP32 accumulate.
+ *   F16_3M  : complex FP16 storage, three real FP16 GEMMs (Gauss form:
+ *             T1 = Ar Br, T2 = Ai Bi, T3 = (Ar+Ai)(Br+Bi); Cr = T1-T2,
+ *             Ci = T3-T1-T2), FP32 accumulate.
+ *   BF16_4M / BF16_3M : the same with bfloat16 storage.
+ * The 16-bit forms keep a power-of-two exponent per tensor and slice (FP64 on
+ * the device); the cross-slice amplitude sum is FP64 in every form. */
+typedef enum {
+    TNC_C64 = 0,
+    TNC_F16_4M = 1,
+    TNC_F16_3M = 2,
+    TNC_BF16_4M = 3,
+    TNC_BF16_3M = 4
+} tnc_precision;
+
+typedef struct tnc_ctx tnc_ctx;
+typedef struct tnc_network tnc_network;
+typedef struct tnc_plan tnc_plan;
+
+/* Static description of a plan (filled by tnc_plan_info / tnc_plan_analyze). */
+typedef struct {
+    int32_t n_steps;               /* pairwise steps in the path                          */
+    int32_t n_dep_steps;           /* steps that depend on the slice (run once per slice) */
+    int32_t n_sliced;              /* sliced labels                                        */
+    int32_t max_rank;              /* largest tensor rank of one slice                     */
+    int32_t slices_in_flight;      /* slices batched through each step (0 before planning) */
+    int32_t out_rank;              /* rank of the final open-qubit tensor                  */
+    double flops_per_slice;        /* algorithmic real flops, 8*B*M*N*K per dependent step */
+    double flops_invariant;        /* the same for slice-invariant steps (once per call)   */
+    double bytes_per_slice;        /* algorithmic HBM bytes of the dependent steps         */
+    double permute_bytes_per_slice;/* the part of bytes_per_slice spent in permutes        */
+    double peak_bytes;             /* arena bytes needed at slices_in_flight               */
+    double peak_elems_per_slice;   /* largest tensor of one slice, in complex entries      */
+} tnc_plan_stats;
+
+/* Results of one tnc_execute. */
+typedef struct {
+    double seconds;                /* device time of the slice block (HIP events)          */
+    double flops;                  /* algorithmic real flops executed                      */
+    int64_t slices;                /* slices summed                                        */
+    int32_t replays;               /* rescale replays after an FP16 range flag             */
+    int32_t graph_launches;        /* graph launches (1 when the block ran as one graph)   */
+} tnc_report;
+
+const char *tnc_last_error(void);
+const char *tnc_version(void);
+
+/* ------------------------------------------------------------------ context */
+
+/* Make a context on HIP device `device`.
+ * workspace / workspace_bytes: caller-owned device memory that holds every
+ *   intermediate tensor (the arena); the library never frees it.  May be NULL
+ *   with workspace_bytes = 0 for a context that only plans.
+ * hip_stream: caller-owned hipStream_t (NULL = the null stream); all device
+ *   work of this context is enqueued on it. */
+int tnc_create(tnc_ctx **out, int device, void *workspace, size_t workspace_bytes, void *hip_stream);
+int tnc_destroy(tnc_ctx *ctx);
+
+/* ------------------------------------------------------------------ network */
+
+/* Describe a network (host only; no device work).
+ * ranks[n_tensors]; labels = the concatenation of every tensor's labels
+ *   (first label slowest), each label id in [0, 2^30);
+ * data_c128: the concatenation of every tensor's 2^rank complex entries as
+ *   interleaved (re, im) doubles; copied.
+ * output_labels[n_qubits]: the open leg of qubit q (its last wire).
+ * A label must occur in exactly two tensors, or in one tensor when it is an
+ * output label; no label may repeat within a tensor.  Otherwise TNC_EINVAL. */
+int tnc_network_create(int32_t n_tensors, const int32_t *ranks, const int32_t *labels,
+                       const double *data_c128, int32_t n_qubits, const int32_t *output_labels,
+                       tnc_network **out);
+int tnc_network_destroy(tnc_network *net);
+
+/* ------------------------------------------------------------------ search */
+
+/* Find a contraction path and sliced labels for `net` with the qubits in
+ * open_qubits[n_open] left open and every other qubit closed.
+ * log2_cap: per-slice limit on the largest tensor, log2 of complex entries.
+ * cost_model: 0 = FLOP/byte cost, 1 = the learned step-time model loaded with
+ *   tnc_costmodel_load (falls back to 0 when none is loaded).
+ * restarts: randomized greedy trials (>= 1); seed makes the result
+ *   deterministic.
+ * ssa_out: host, capacity 2*(n_tensors-1) ints; receives the path as
+ *   single-static-assignment pairs (ids >= n_tensors name step results).
+ * sliced_out: host, capacity max_sliced; receives sliced label ids.
+ * n_sliced: host out.  log2_cost_out (may be NULL): log2 of total real flops
+ *   over all slices under the FLOP model. */
+int tnc_search(const tnc_network *net, int32_t n_open, const int32_t *open_qubits, double log2_cap,
+               int32_t cost_model, int32_t restarts, uint64_t seed, int32_t *ssa_out,
+               int32_t max_sliced, int32_t *sliced_out, int32_t *n_sliced, double *log2_cost_out);
+
+/* ------------------------------------------------------------------ plan */
+
+/* Compile a path for execution on ctx's device.
+ * ssa_pairs[2*n_steps]: the path (a full binary tree over all tensors).
+ * sliced_labels[n_sliced]: labels fixed per slice; slice s sets
+ *   sliced_labels[j] to bit j of s.  Must not be output labels.
+ * open_qubits[n_open]: qubits whose output labels stay open; the others are
+ *   closed with the values the bitstrings give them at execute time.
+ * max_slices_in_flight: upper bound on slices batched through each step
+ *   (0 = as many as the workspace holds, at most 2^n_sliced).
+ * Errors: TNC_EINVAL (path or labels), TNC_ENOMEM (one slice does not fit the
+ *   workspace), TNC_EDEVICE. */
+int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                    int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
+                    const int32_t *open_qubits, tnc_precision prec, int32_t max_slices_in_flight,
+                    tnc_plan **out);
+int tnc_plan_destroy(tnc_plan *plan);
+int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats);
+
+/* Host-only analysis of a path (no context, no device): fills `stats` for
+ * one slice (slices_in_flight = 0, peak_bytes for one slice). */
+int tnc_plan_analyze(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                     int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
+                     const int32_t *open_qubits, tnc_precision prec, tnc_plan_stats *stats);
+
+/* Sum the amplitudes of slices [slice_begin, slice_end) for each bitstring.
+ * bitstrings: host, n_bitstrings values; they must agree on every closed qubit
+ *   (TNC_EINVAL otherwise); duplicates are allowed.
+ * out_c128: 2*n_bitstrings doubles (re, im), host or device memory on the
+ *   context's device; receives the FP64 partial sums, so disjoint ranges add.
+ * rep: may be NULL.
+ * Slices in [slice_begin, slice_end) run as one graph launch on the context's
+ * stream; the call returns after the result is in out_c128. */
+int tnc_execute(tnc_plan *plan, int64_t n_bitstrings, const uint64_t *bitstrings, int64_t slice_begin,
+                int64_t slice_end, double *out_c128, tnc_report *rep);
+
+/* Per-step device times of the last tnc_execute run with step timing on
+ * (tnc_plan_set_timing; timed runs launch step by step, not as one graph).
+ * Host arrays of capacity n_steps (each may be NULL): gemm_ms[t] and
+ * permute_ms[t] are the summed HIP-event times of step t's GEMM launches and
+ * operand permutes over the call, launches[t] the number of GEMM launches
+ * (one per slice group for a slice-dependent step). */
+int tnc_plan_set_timing(tnc_plan *plan, int32_t on);
+int tnc_plan_step_times(const tnc_plan *plan, int32_t n_steps, double *gemm_ms, double *permute_ms,
+                        int32_t *launches);
+
+/* Per-step static description (host arrays of capacity n_steps, each may be
+ * NULL): log2 of M, N, K and of the inner batch; the kernel variant id; 1 if
+ * the step depends on the slice; 1/0 if its A / B operand is permuted;
+ * algorithmic real flops per slice (8 B M N K) and GEMM bytes per slice
+ * (A + B + C at the storage size). */
+int tnc_plan_steps(const tnc_plan *plan, int32_t n_steps, int32_t *log2_mnkb /* 4 per step */,
+                   int32_t *kernel, int32_t *dep, int32_t *perm_ab /* 2 per step */, double *flops,
+                   double *bytes);
+
+/* ------------------------------------------------------------------ one contraction */
+
+/* One pairwise contraction C = A . B on device-resident operands (paper
+ * Eq. contraction), used by the step microbenchmark.
+ * A, B, C: device, complex storage of `prec` (C64: 8-byte float pairs;
+ *   16-bit forms: 4-byte (re, im) pairs), ranks a_rank/b_rank/c_rank with the
+ *   given label lists (first label slowest).  Labels of C must be a subset of
+ *   those of A and B; labels of A and B missing from C must occur in both.
+ * scale_log2: 16-bit forms store C * 2^-scale_log2 (exact power of two).
+ * times_ms: host, 4 doubles or NULL: permute(A), permute(B), GEMM, permute(C)
+ *   device times of this call.
+ * max_abs_out: host, 1 float or NULL: largest |re| or |im| stored in C. */
+int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int32_t a_rank,
+                 const int32_t *a_labels, const void *B, int32_t b_rank, const int32_t *b_labels,
+                 void *C, int32_t c_rank, const int32_t *c_labels, int32_t scale_log2,
+                 double *times_ms, float *max_abs_out);
+
+/* ------------------------------------------------------------------ learned step-cost model */
+
+/* Step-time MLP (3 Linear layers, in -> 128 -> 128 -> 1, ReLU, FP32), trained
+ * on the device by the library's own forward, backward and Adam kernels.
+ * Feature row layout (TNC_MLP_FEATURES floats): log2 M, log2 N, log2 K,
+ * log2 batch, stride class of A, stride class of B, dtype (0 c64, 1 f16,
+ * 2 bf16), algorithm (0 4M, 1 3M).  Target: log2 of the step time in
+ * microseconds. */
+#define TNC_MLP_FEATURES 8
+#define TNC_MLP_HIDDEN 128
+
+/* Train from scratch on n rows (host arrays x[n*TNC_MLP_FEATURES], y[n]) for
+ * `epochs` epochs of minibatches of `batch` rows, Adam with learning rate lr,
+ * initial weights from `seed`.  loss_out (host, may be NULL): final mean
+ * squared error on the training rows.  The trained weights become the
+ * context's cost model. */
+int tnc_mlp_train(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32_t epochs,
+                  int32_t batch, float lr, uint64_t seed, float *loss_out);
+/* Predict n rows (host in, host out). */
+int tnc_mlp_predict(tnc_ctx *ctx, int64_t n, const float *x, float *y_out);
+/* One forward + backward pass on n rows with the current weights: loss (MSE)
+ * and the gradient of every parameter, concatenated in the order W1, b1, W2,
+ * b2, W3, b3 (W row-major [out][in]); grads_out host, tnc_mlp_param_count()
+ * floats.  Used to check gradients. */
+int tnc_mlp_grad(tnc_ctx *ctx, int64_t n, const float *x, const float *y, float *loss_out,
+                 float *grads_out);
+int64_t tnc_mlp_param_count(void);
+/* Copy weights out / in (host, tnc_mlp_param_count() floats, same order). */
+int tnc_mlp_get_params(tnc_ctx *ctx, float *params_out);
+int tnc_mlp_set_params(tnc_ctx *ctx, const float *params);
+/* Make the context's MLP the cost model used by tnc_search(cost_model = 1)
+ * on this thread. */
+int tnc_costmodel_use(tnc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNC_H */

@@ -1,0 +1,318 @@
+"""ctypes binding of libtnc (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps and does no
+arithmetic of its own: it converts numpy arrays and torch tensors to
+pointers, calls the library, raises ``TncError`` on a nonzero return code and
+returns the outputs.  The library is loaded from this package directory;
+importing this module fails loudly when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtnc.so")
+
+TNC_C64, TNC_F16_4M, TNC_F16_3M, TNC_BF16_4M, TNC_BF16_3M = 0, 1, 2, 3, 4
+PRECISIONS = {"c64": TNC_C64, "f16_4m": TNC_F16_4M, "f16_3m": TNC_F16_3M, "bf16_4m": TNC_BF16_4M,
+              "bf16_3m": TNC_BF16_3M}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "EUNSUPPORTED"}
+MLP_FEATURES = 8
+MLP_HIDDEN = 128
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+c_int32_p = ctypes.POINTER(ctypes.c_int32)
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_float_p = ctypes.POINTER(ctypes.c_float)
+c_u64_p = ctypes.POINTER(ctypes.c_uint64)
+vp = ctypes.c_void_p
+
+
+class tnc_plan_stats(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("n_dep_steps", ctypes.c_int32), ("n_sliced", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32), ("slices_in_flight", ctypes.c_int32), ("out_rank", ctypes.c_int32),
+                ("flops_per_slice", ctypes.c_double), ("flops_invariant", ctypes.c_double),
+                ("bytes_per_slice", ctypes.c_double), ("permute_bytes_per_slice", ctypes.c_double),
+                ("peak_bytes", ctypes.c_double), ("peak_elems_per_slice", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class tnc_report(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("flops", ctypes.c_double), ("slices", ctypes.c_int64),
+                ("replays", ctypes.c_int32), ("graph_launches", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS = {
+    "tnc_last_error": (ctypes.c_char_p, []),
+    "tnc_version": (ctypes.c_char_p, []),
+    "tnc_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_size_t, vp]),
+    "tnc_destroy": (ctypes.c_int, [vp]),
+    "tnc_network_create": (ctypes.c_int, [ctypes.c_int32, c_int32_p, c_int32_p, c_double_p, ctypes.c_int32,
+                                          c_int32_p, ctypes.POINTER(vp)]),
+    "tnc_network_destroy": (ctypes.c_int, [vp]),
+    "tnc_search": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_uint64, c_int32_p, ctypes.c_int32, c_int32_p, c_int32_p, c_double_p]),
+    "tnc_plan_create": (ctypes.c_int, [vp, vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
+                                       ctypes.c_int32, c_int32_p, ctypes.c_int, ctypes.c_int32,
+                                       ctypes.POINTER(vp)]),
+    "tnc_plan_destroy": (ctypes.c_int, [vp]),
+    "tnc_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(tnc_plan_stats)]),
+    "tnc_plan_analyze": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p, ctypes.c_int32,
+                                        c_int32_p, ctypes.c_int, ctypes.POINTER(tnc_plan_stats)]),
+    "tnc_execute": (ctypes.c_int, [vp, ctypes.c_int64, c_u64_p, ctypes.c_int64, ctypes.c_int64, vp,
+                                   ctypes.POINTER(tnc_report)]),
+    "tnc_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int32]),
+    "tnc_plan_step_times": (ctypes.c_int, [vp, ctypes.c_int32, c_double_p, c_double_p, c_int32_p]),
+    "tnc_plan_steps": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, c_int32_p, c_int32_p, c_int32_p, c_double_p,
+                                      c_double_p]),
+    "tnc_contract": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_int32, c_int32_p, vp, ctypes.c_int32, c_int32_p,
+                                    vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_double_p, c_float_p]),
+    "tnc_mlp_train": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_float, ctypes.c_uint64, c_float_p]),
+    "tnc_mlp_predict": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p]),
+    "tnc_mlp_grad": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, c_float_p, c_float_p]),
+    "tnc_mlp_param_count": (ctypes.c_int64, []),
+    "tnc_mlp_get_params": (ctypes.c_int, [vp, c_float_p]),
+    "tnc_mlp_set_params": (ctypes.c_int, [vp, c_float_p]),
+    "tnc_costmodel_use": (ctypes.c_int, [vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class TncError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise TncError(rc, lib.tnc_last_error().decode())
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(c_int32_p)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor, or an int address."""
+    return ctypes.c_void_p(t if isinstance(t, int) else t.data_ptr())
+
+
+def tnc_last_error() -> str:
+    return lib.tnc_last_error().decode()
+
+
+def tnc_version() -> str:
+    return lib.tnc_version().decode()
+
+
+def tnc_create(device: int, workspace=None, workspace_bytes: int = 0, stream=None):
+    """workspace: torch uint8 tensor on the device (caller keeps it alive);
+    stream: torch.cuda.Stream, an int hipStream_t, or None."""
+    h = vp()
+    ws = vp(0) if workspace is None else _dptr(workspace)
+    nbytes = workspace_bytes if workspace is None else workspace.numel() * workspace.element_size()
+    if stream is None:
+        sp = vp(0)
+    elif isinstance(stream, int):
+        sp = vp(stream)
+    else:
+        sp = vp(stream.cuda_stream)
+    _check(lib.tnc_create(ctypes.byref(h), int(device), ws, ctypes.c_size_t(nbytes), sp))
+    return h
+
+
+def tnc_destroy(ctx):
+    _check(lib.tnc_destroy(ctx))
+
+
+def tnc_network_create(ranks, labels, data_c128, n_qubits, output_labels):
+    r, rp = _i32(ranks)
+    lab, lp = _i32(labels)
+    d = None
+    dp = None
+    if data_c128 is not None:
+        d = np.ascontiguousarray(data_c128, dtype=np.float64)
+        dp = d.ctypes.data_as(c_double_p)
+    o, op = _i32(output_labels)
+    h = vp()
+    _check(lib.tnc_network_create(len(r), rp, lp, dp, int(n_qubits), op, ctypes.byref(h)))
+    return h
+
+
+def tnc_network_destroy(net):
+    _check(lib.tnc_network_destroy(net))
+
+
+def tnc_search(net, n_tensors, open_qubits, log2_cap, cost_model=0, restarts=8, seed=0, max_sliced=62):
+    oq, op = _i32(open_qubits)
+    ssa = np.zeros(2 * (n_tensors - 1), dtype=np.int32)
+    sl = np.zeros(max(max_sliced, 1), dtype=np.int32)
+    ns = ctypes.c_int32(0)
+    cost = ctypes.c_double(0)
+    _check(lib.tnc_search(net, len(oq), op, float(log2_cap), int(cost_model), int(restarts), ctypes.c_uint64(seed),
+                          ssa.ctypes.data_as(c_int32_p), int(max_sliced), sl.ctypes.data_as(c_int32_p),
+                          ctypes.byref(ns), ctypes.byref(cost)))
+    return ssa, sl[:ns.value].copy(), cost.value
+
+
+def tnc_plan_create(ctx, net, ssa, sliced, open_qubits, precision, max_slices_in_flight=0):
+    s, sp = _i32(ssa)
+    sl, slp = _i32(sliced)
+    oq, op = _i32(open_qubits)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    h = vp()
+    _check(lib.tnc_plan_create(ctx, net, len(s) // 2, sp, len(sl), slp, len(oq), op, prec,
+                               int(max_slices_in_flight), ctypes.byref(h)))
+    return h
+
+
+def tnc_plan_destroy(plan):
+    _check(lib.tnc_plan_destroy(plan))
+
+
+def tnc_plan_info(plan) -> dict:
+    st = tnc_plan_stats()
+    _check(lib.tnc_plan_info(plan, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def tnc_plan_analyze(net, ssa, sliced, open_qubits, precision) -> dict:
+    s, sp = _i32(ssa)
+    sl, slp = _i32(sliced)
+    oq, op = _i32(open_qubits)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    st = tnc_plan_stats()
+    _check(lib.tnc_plan_analyze(net, len(s) // 2, sp, len(sl), slp, len(oq), op, prec, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def tnc_execute(plan, bitstrings, slice_begin, slice_end, out=None):
+    """out: None (a new host complex128 array is returned), a host complex128
+    array, or a torch float64/complex128 device tensor of 2*n doubles."""
+    b = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+    rep = tnc_report()
+    if out is None:
+        host = np.zeros(len(b), dtype=np.complex128)
+        optr = vp(host.ctypes.data)
+    elif isinstance(out, np.ndarray):
+        assert out.dtype == np.complex128 and out.flags.c_contiguous and len(out) == len(b)
+        host = out
+        optr = vp(out.ctypes.data)
+    else:
+        host = None
+        optr = _dptr(out)
+    _check(lib.tnc_execute(plan, len(b), b.ctypes.data_as(c_u64_p), int(slice_begin), int(slice_end), optr,
+                           ctypes.byref(rep)))
+    return (host if host is not None else out), rep.as_dict()
+
+
+def tnc_plan_set_timing(plan, on: bool):
+    _check(lib.tnc_plan_set_timing(plan, int(bool(on))))
+
+
+def tnc_plan_step_times(plan, n_steps):
+    """(gemm_ms, permute_ms, launches) per step of the last timed execute."""
+    g = np.zeros(n_steps, dtype=np.float64)
+    p = np.zeros(n_steps, dtype=np.float64)
+    n = np.zeros(n_steps, dtype=np.int32)
+    _check(lib.tnc_plan_step_times(plan, n_steps, g.ctypes.data_as(c_double_p), p.ctypes.data_as(c_double_p),
+                                   n.ctypes.data_as(c_int32_p)))
+    return g, p, n
+
+
+def tnc_plan_steps(plan, n_steps) -> dict:
+    """Static per-step shapes, kernels and algorithmic work."""
+    mnkb = np.zeros(4 * n_steps, dtype=np.int32)
+    kern = np.zeros(n_steps, dtype=np.int32)
+    dep = np.zeros(n_steps, dtype=np.int32)
+    pab = np.zeros(2 * n_steps, dtype=np.int32)
+    fl = np.zeros(n_steps, dtype=np.float64)
+    by = np.zeros(n_steps, dtype=np.float64)
+    _check(lib.tnc_plan_steps(plan, n_steps, mnkb.ctypes.data_as(c_int32_p), kern.ctypes.data_as(c_int32_p),
+                              dep.ctypes.data_as(c_int32_p), pab.ctypes.data_as(c_int32_p),
+                              fl.ctypes.data_as(c_double_p), by.ctypes.data_as(c_double_p)))
+    return {"log2_mnkb": mnkb.reshape(-1, 4), "kernel": kern, "dep": dep, "perm_ab": pab.reshape(-1, 2),
+            "flops": fl, "bytes": by}
+
+
+def tnc_contract(ctx, precision, A, a_labels, B, b_labels, C, c_labels, scale_log2=0):
+    al, ap = _i32(a_labels)
+    bl, bp = _i32(b_labels)
+    cl, cp = _i32(c_labels)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    times = np.zeros(4, dtype=np.float64)
+    mx = ctypes.c_float(0)
+    _check(lib.tnc_contract(ctx, prec, _dptr(A), len(al), ap, _dptr(B), len(bl), bp, _dptr(C), len(cl), cp,
+                            int(scale_log2), times.ctypes.data_as(c_double_p), ctypes.byref(mx)))
+    return times, mx.value
+
+
+def tnc_mlp_param_count() -> int:
+    return int(lib.tnc_mlp_param_count())
+
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(c_float_p)
+
+
+def tnc_mlp_train(ctx, x, y, epochs, batch, lr, seed):
+    xa, xp = _f32(x)
+    ya, yp = _f32(y)
+    loss = ctypes.c_float(0)
+    _check(lib.tnc_mlp_train(ctx, len(ya), xp, yp, int(epochs), int(batch), float(lr), ctypes.c_uint64(seed),
+                             ctypes.byref(loss)))
+    return loss.value
+
+
+def tnc_mlp_predict(ctx, x):
+    xa, xp = _f32(x)
+    n = xa.shape[0]
+    y = np.zeros(n, dtype=np.float32)
+    _check(lib.tnc_mlp_predict(ctx, n, xp, y.ctypes.data_as(c_float_p)))
+    return y
+
+
+def tnc_mlp_grad(ctx, x, y):
+    xa, xp = _f32(x)
+    ya, yp = _f32(y)
+    g = np.zeros(tnc_mlp_param_count(), dtype=np.float32)
+    loss = ctypes.c_float(0)
+    _check(lib.tnc_mlp_grad(ctx, len(ya), xp, yp, ctypes.byref(loss), g.ctypes.data_as(c_float_p)))
+    return loss.value, g
+
+
+def tnc_mlp_get_params(ctx):
+    p = np.zeros(tnc_mlp_param_count(), dtype=np.float32)
+    _check(lib.tnc_mlp_get_params(ctx, p.ctypes.data_as(c_float_p)))
+    return p
+
+
+def tnc_mlp_set_params(ctx, params):
+    pa, pp = _f32(params)
+    assert len(pa) == tnc_mlp_param_count()
+    _check(lib.tnc_mlp_set_params(ctx, pp))
+
+
+def tnc_costmodel_use(ctx):
+    _check(lib.tnc_costmodel_use(ctx))

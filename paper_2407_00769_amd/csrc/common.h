@@ -1,0 +1,144 @@
+// Internal declarations shared by the host planner, the executor and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tnc.h"
+
+namespace tnc {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define TNC_THROW(code, msg)                                  \
+    do {                                                      \
+        throw ::tnc::Error{(code), std::string(msg)};         \
+    } while (0)
+
+#define HIP_CHECK(expr)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw ::tnc::Error{TNC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+// ------------------------------------------------------------------ element kinds
+enum class Dtype : int { C64 = 0, F16 = 1, BF16 = 2 };
+enum class Algo : int { M4 = 0, M3 = 1 };
+
+inline Dtype dtype_of(tnc_precision p) {
+    switch (p) {
+        case TNC_C64: return Dtype::C64;
+        case TNC_F16_4M:
+        case TNC_F16_3M: return Dtype::F16;
+        default: return Dtype::BF16;
+    }
+}
+inline Algo algo_of(tnc_precision p) {
+    return (p == TNC_F16_3M || p == TNC_BF16_3M) ? Algo::M3 : Algo::M4;
+}
+inline int elem_bytes(Dtype d) { return d == Dtype::C64 ? 8 : 4; }
+
+// ------------------------------------------------------------------ network (host)
+struct Network {
+    int n_tensors = 0;
+    std::vector<std::vector<int>> labels;      // per tensor, first label slowest
+    std::vector<std::vector<double>> data;     // per tensor, interleaved complex128
+    int n_qubits = 0;
+    std::vector<int> output_labels;            // per qubit
+    int n_labels = 0;                          // 1 + max label id
+};
+
+// ------------------------------------------------------------------ kernel launch descriptors
+
+// Bit permutation of a batch of tensors.  Destination element j of slice s
+// reads source element  src_base(s) + sum_b bit_b(j) * src_stride[b].
+constexpr int kMaxRank = 48;
+struct PermuteDesc {
+    int rank;                   // destination rank
+    int64_t src_stride[kMaxRank];  // element stride in the source for destination bit b (bit 0 = fastest)
+};
+
+// Everything one step needs at run time.  Sizes are complex entries.
+struct GemmShape {
+    int64_t M, N, K, nb;        // rows, cols, reduced, inner batch
+    int64_t sA, sB, sC;         // slice strides (0 = shared by every slice)
+    int64_t bA, bB, bC;         // inner-batch strides
+};
+
+// Scale bookkeeping of the 16-bit forms, per tensor and slice.
+struct ScaleRefs {
+    const uint32_t *maxA; int mA;   // max |re|,|im| (float bits); index s*mA
+    const uint32_t *maxB; int mB;
+    uint32_t *maxC;                 // written with atomicMax, index s
+    const double *expA; int eA;     // power-of-two exponents, index s*eA
+    const double *expB; int eB;
+    double *expC;                   // index s
+    int *shift;                     // per slice (written), may be null
+    const int *growth;              // device int: expected log2 growth of this step
+    uint32_t *flag;                 // set nonzero on range overflow
+};
+
+// Kernel variant ids (autotuned per step).
+enum KernelId : int {
+    K_NAIVE = 0,      // thread per output entry; any shape
+    K_SKINNY_N = 1,   // row per thread, N <= 16, VALU
+    K_MFMA_S = 2,     // matrix-core tile 64 x 32c
+    K_MFMA_M = 3,     // matrix-core tile 128 x 32c
+    K_MFMA_L = 4,     // matrix-core tile 128 x 64c
+    K_MFMA_W = 5,     // matrix-core tile 256 x 16c (thin N)
+    K_COUNT = 6
+};
+const char *kernel_name(int k);
+
+// Launch wrappers (kernels.hip).
+void launch_permute(Dtype dt, const void *src, void *dst, const PermuteDesc &d, int64_t n_out,
+                    int S, int64_t src_slice_stride, const int64_t *d_slice_offsets,
+                    int64_t dst_slice_stride, hipStream_t st);
+bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g);
+void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void *C,
+                 const GemmShape &g, int S, const ScaleRefs *sc, hipStream_t st);
+void launch_convert_c128(const double *src, int64_t n, Dtype dt, void *dst, hipStream_t st);
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
+void launch_tensor_max(Dtype dt, const void *x, int64_t n, int S, int64_t slice_stride,
+                       uint32_t *max_out, hipStream_t st);
+void launch_accumulate(Dtype dt, const void *R, int rank, int S, int64_t slice_stride,
+                       const double *expR, int n_exp_stride, int64_t nbits, const uint64_t *d_bits,
+                       const int *d_qubit_of_bit, double *acc, hipStream_t st);
+
+// Bits of an LDS-tiled permute: destination bits hi[i] hold source bits i
+// (i < w); rest lists the destination bits outside both w-bit sets.
+struct TileBits {
+    int hi[8];
+    int rest[kMaxRank];
+    int n_rest;
+};
+bool plan_tile_bits(const PermuteDesc &d, int lw, TileBits &tb);
+
+// Slice selection of one input tensor (see gather_leaves_kernel).
+constexpr int kMaxLeafRank = 16;
+struct LeafDesc {
+    int64_t src_off;            // element offset of the full tensor in the leaf buffer
+    int64_t closed_off;         // element offset from the closed-qubit values of this call
+    int64_t dst_byte_off;       // arena byte offset of slice 0
+    int64_t dst_slice_stride;   // elements between consecutive slices
+    int64_t stride[kMaxLeafRank];        // source stride of destination bit b
+    int64_t slice_stride[kMaxLeafRank];  // source stride of sliced label j
+    int slice_bit[kMaxLeafRank];         // bit of the slice id that sets sliced label j
+    int rank, n_sliced, n_slices, max_slot, slot_stride, pad_;
+};
+void launch_gather_leaves_impl(Dtype dt, int n_leaves, const LeafDesc *d_desc, const int64_t *d_params,
+                               const void *leafdata, uint8_t *arena, uint32_t *maxw, double *expw,
+                               int group_base, int S, hipStream_t st);
+
+}  // namespace tnc

@@ -1,0 +1,639 @@
+// C-ABI entry points: context, network, plan, execution of a slice block,
+// one-off contraction.  Every step of a slice runs in the library's HIP
+// kernels; the host only validates, plans and enqueues.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <set>
+
+#include "planner.h"
+
+using namespace tnc;
+
+namespace tnc {
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace tnc
+
+extern "C" const char *tnc_last_error(void) { return tnc::g_err.c_str(); }
+extern "C" const char *tnc_version(void) { return "tnc 0.1 (gfx950)"; }
+
+#define API_BEGIN try {
+#define API_END                                            \
+    }                                                      \
+    catch (const tnc::Error &e) {                          \
+        tnc::set_error(e.msg);                             \
+        return e.code;                                     \
+    }                                                      \
+    catch (const std::bad_alloc &) {                       \
+        tnc::set_error("host allocation failed");          \
+        return TNC_ENOMEM;                                 \
+    }                                                      \
+    catch (const std::exception &e) {                      \
+        tnc::set_error(e.what());                          \
+        return TNC_EINVAL;                                 \
+    }                                                      \
+    return TNC_OK;
+
+#define REQUIRE(cond, msg) \
+    do {                   \
+        if (!(cond)) TNC_THROW(TNC_EINVAL, msg); \
+    } while (0)
+
+// ------------------------------------------------------------------ context
+
+extern "C" int tnc_create(tnc_ctx **out, int device, void *workspace, size_t workspace_bytes, void *hip_stream) {
+    API_BEGIN
+    REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_CHECK(hipGetDeviceCount(&n));
+    REQUIRE(device >= 0 && device < n, "device out of range");
+    REQUIRE(workspace || workspace_bytes == 0, "workspace is NULL but workspace_bytes > 0");
+    HIP_CHECK(hipSetDevice(device));
+    auto *c = new tnc_ctx;
+    c->device = device;
+    c->ws = (uint8_t *)workspace;
+    c->ws_bytes = workspace_bytes;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipMalloc((void **)&c->small, 4096);
+    if (e != hipSuccess) {
+        delete c;
+        TNC_THROW(TNC_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    API_END
+}
+
+extern "C" int tnc_destroy(tnc_ctx *ctx) {
+    API_BEGIN
+    if (!ctx) return TNC_OK;
+    hipSetDevice(ctx->device);
+    if (ctx->small) hipFree(ctx->small);
+    if (ctx->mlp) mlp_free(ctx->mlp);
+    delete ctx;
+    API_END
+}
+
+// ------------------------------------------------------------------ network
+
+extern "C" int tnc_network_create(int32_t n_tensors, const int32_t *ranks, const int32_t *labels,
+                                  const double *data_c128, int32_t n_qubits, const int32_t *output_labels,
+                                  tnc_network **out) {
+    API_BEGIN
+    REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    REQUIRE(n_tensors >= 1, "n_tensors < 1");
+    REQUIRE(ranks && labels, "ranks or labels is NULL");
+    REQUIRE(n_qubits >= 0 && n_qubits <= 64, "n_qubits must be in [0, 64]");
+    REQUIRE(n_qubits == 0 || output_labels, "output_labels is NULL");
+    auto *nw = new tnc_network;
+    Network &net = nw->net;
+    try {
+        net.n_tensors = n_tensors;
+        net.labels.resize(n_tensors);
+        net.data.resize(n_tensors);
+        int64_t lp = 0, dp = 0;
+        int maxl = -1;
+        for (int i = 0; i < n_tensors; i++) {
+            REQUIRE(ranks[i] >= 0 && ranks[i] <= 30, "tensor rank out of [0, 30]");
+            for (int j = 0; j < ranks[i]; j++) {
+                int l = labels[lp++];
+                REQUIRE(l >= 0 && l < (1 << 30), "label id out of range");
+                net.labels[i].push_back(l);
+                maxl = std::max(maxl, l);
+            }
+            std::vector<int> sorted = net.labels[i];
+            std::sort(sorted.begin(), sorted.end());
+            REQUIRE(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(),
+                    "tensor " + std::to_string(i) + " repeats a label");
+            int64_t n = (int64_t)1 << ranks[i];
+            if (data_c128) net.data[i].assign(data_c128 + 2 * dp, data_c128 + 2 * (dp + n));
+            else net.data[i].assign(2 * n, 0.0);
+            dp += n;
+        }
+        net.n_labels = maxl + 1;
+        REQUIRE(net.n_labels <= (1 << 24), "label ids must be below 2^24 (dense ids expected)");
+        std::vector<int> cnt(net.n_labels, 0), is_out(net.n_labels, 0);
+        for (auto &v : net.labels)
+            for (int l : v) cnt[l]++;
+        net.n_qubits = n_qubits;
+        for (int q = 0; q < n_qubits; q++) {
+            int l = output_labels[q];
+            REQUIRE(l >= 0 && l < net.n_labels && cnt[l] >= 1, "output label of qubit " + std::to_string(q) + " not in the network");
+            REQUIRE(!is_out[l], "two qubits share an output label");
+            is_out[l] = 1;
+            net.output_labels.push_back(l);
+        }
+        for (int l = 0; l < net.n_labels; l++) {
+            if (cnt[l] == 0) continue;
+            if (is_out[l]) REQUIRE(cnt[l] == 1, "output label " + std::to_string(l) + " occurs in more than one tensor");
+            else REQUIRE(cnt[l] == 2, "label " + std::to_string(l) + " must occur in exactly two tensors");
+        }
+    } catch (...) {
+        delete nw;
+        throw;
+    }
+    *out = nw;
+    API_END
+}
+
+extern "C" int tnc_network_destroy(tnc_network *net) {
+    delete net;
+    return TNC_OK;
+}
+
+// ------------------------------------------------------------------ plan
+
+static void free_plan_device(tnc_plan *p) {
+    for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    void *ptrs[] = {p->d_leafdata, p->d_desc, p->d_maxw, p->d_expw, p->d_shift, p->d_growth,
+                    p->d_flags,    p->d_params, p->d_bits, p->d_acc, p->d_qob};
+    for (void *q : ptrs)
+        if (q) hipFree(q);
+}
+
+template <typename T> static T *dev_alloc(int64_t count) {
+    T *p = nullptr;
+    HIP_CHECK(hipMalloc((void **)&p, sizeof(T) * std::max<int64_t>(count, 1)));
+    return p;
+}
+
+static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
+    Analysis &an = p->an;
+    tnc_ctx *ctx = p->ctx;
+    const int nT = net.n_tensors;
+    p->nT = nT;
+    p->n_qubits = net.n_qubits;
+    p->output_labels = net.output_labels;
+    p->leaf_orig_labels = net.labels;
+    for (int q = 0; q < net.n_qubits; q++)
+        if (an.fixed[net.output_labels[q]] == 1) p->closed_qubits.push_back(q);
+    // slices in flight: as many as fit, at most the slice count
+    int64_t n_slices_total = (int64_t)1 << an.n_sliced;
+    int64_t cap = n_slices_total;
+    if (max_sif > 0) cap = std::min<int64_t>(cap, max_sif);
+    cap = std::min<int64_t>(cap, 4096);
+    int64_t peak1 = plan_memory(an, 1, false);
+    if ((size_t)peak1 > ctx->ws_bytes)
+        TNC_THROW(TNC_ENOMEM, "one slice needs " + std::to_string(peak1) + " workspace bytes, have " +
+                                  std::to_string(ctx->ws_bytes));
+    int S = 1;
+    while (S * 2 <= cap && (size_t)plan_memory(an, S * 2, false) <= ctx->ws_bytes) S *= 2;
+    p->S = S;
+    p->peak = plan_memory(an, S, true);
+
+    HIP_CHECK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const Dtype dt = an.dt;
+    const int es = elem_bytes(dt);
+    // input tensors: upload complex128, convert on the device
+    int64_t total = 0;
+    std::vector<int64_t> leaf_off(nT);
+    for (int i = 0; i < nT; i++) {
+        leaf_off[i] = total;
+        total += (int64_t)net.data[i].size() / 2;
+    }
+    p->d_leafdata = dev_alloc<uint8_t>(total * es);
+    {
+        double *tmp = dev_alloc<double>(2 * total);
+        std::vector<double> h(2 * total);
+        for (int i = 0; i < nT; i++) std::copy(net.data[i].begin(), net.data[i].end(), h.begin() + 2 * leaf_off[i]);
+        HIP_CHECK(hipMemcpyAsync(tmp, h.data(), sizeof(double) * 2 * total, hipMemcpyHostToDevice, st));
+        launch_convert_c128(tmp, total, dt, p->d_leafdata, st);
+        HIP_CHECK(hipStreamSynchronize(st));
+        hipFree(tmp);
+    }
+    // leaf descriptors: invariant first, then dependent
+    std::vector<int> inv, dep;
+    for (int i = 0; i < nT; i++) (an.tensors[i].dep ? dep : inv).push_back(i);
+    p->n_inv_leaves = (int)inv.size();
+    p->n_dep_leaves = (int)dep.size();
+    p->desc_of_leaf.assign(nT, -1);
+    std::vector<int> order = inv;
+    order.insert(order.end(), dep.begin(), dep.end());
+    for (int i : order) {
+        const TensorRec &t = an.tensors[i];
+        LeafDesc d{};
+        d.src_off = leaf_off[i];
+        d.dst_byte_off = t.off;
+        d.dst_slice_stride = t.dep ? ((int64_t)1 << t.rank()) : 0;
+        d.rank = t.rank();
+        const auto &orig = net.labels[i];
+        const int ro = (int)orig.size();
+        for (int b = 0; b < d.rank; b++) {
+            int l = t.labels[d.rank - 1 - b];
+            int pos = ro - 1 - (int)(std::find(orig.begin(), orig.end(), l) - orig.begin());
+            d.stride[b] = (int64_t)1 << pos;
+        }
+        for (int j = 0; j < ro; j++) {
+            int l = orig[j];
+            if (an.fixed[l] == 0) {
+                d.slice_bit[d.n_sliced] = an.slice_bit[l];
+                d.slice_stride[d.n_sliced] = (int64_t)1 << (ro - 1 - j);
+                d.n_sliced++;
+            }
+        }
+        d.n_slices = t.dep ? S : 1;
+        d.max_slot = i * S;
+        d.slot_stride = t.dep ? 1 : 0;
+        p->desc_of_leaf[i] = (int)p->h_desc.size();
+        p->h_desc.push_back(d);
+    }
+    p->d_desc = dev_alloc<LeafDesc>((int64_t)p->h_desc.size());
+    HIP_CHECK(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(LeafDesc) * p->h_desc.size(),
+                             hipMemcpyHostToDevice, st));
+    p->closed_state.assign(nT, 0);
+    const int64_t nslots = (int64_t)an.tensors.size() * S;
+    p->d_maxw = dev_alloc<uint32_t>(nslots);
+    p->d_expw = dev_alloc<double>(nslots);
+    p->d_shift = dev_alloc<int>(nslots);
+    const int ns = (int)an.steps.size();
+    p->d_growth = dev_alloc<int>(ns);
+    p->d_flags = dev_alloc<uint32_t>(ns);
+    p->h_growth.resize(ns);
+    for (int s = 0; s < ns; s++) {
+        // expected log2 of max|C| / (max|A| max|B|): about half of log2 K for
+        // random phases, plus one bit of margin
+        int kb = (int)an.steps[s].k.size();
+        p->h_growth[s] = (kb + 1) / 2 + 1;
+    }
+    HIP_CHECK(hipMemcpyAsync(p->d_growth, p->h_growth.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+    launch_fill_u32(p->d_flags, 0, ns, st);
+    launch_fill_f64(p->d_expw, 0.0, nslots, st);
+    p->d_params = dev_alloc<int64_t>(4);
+    const TensorRec &R = an.tensors[an.root];
+    std::vector<int> qob(std::max(1, R.rank()));
+    for (int b = 0; b < R.rank(); b++) qob[b] = an.open_qubit_of_label[R.labels[R.rank() - 1 - b]];
+    p->d_qob = dev_alloc<int>((int64_t)qob.size());
+    HIP_CHECK(hipMemcpyAsync(p->d_qob, qob.data(), sizeof(int) * qob.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    p->step_ms.assign(ns, 0.0);
+    p->perm_ms.assign(ns, 0.0);
+    p->step_launches.assign(ns, 0);
+    const char *ng = getenv("TNC_NO_GRAPH");
+    // graphs are captured on the context's stream; the legacy null stream cannot be captured
+    p->use_graph = !(ng && ng[0] == '1') && ctx->stream != nullptr;
+}
+
+extern "C" int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                               int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
+                               const int32_t *open_qubits, tnc_precision prec, int32_t max_slices_in_flight,
+                               tnc_plan **out) {
+    API_BEGIN
+    REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    REQUIRE(ctx && net, "ctx or net is NULL");
+    REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
+    REQUIRE(n_sliced == 0 || sliced_labels, "sliced_labels is NULL");
+    REQUIRE(n_open == 0 || open_qubits, "open_qubits is NULL");
+    auto *p = new tnc_plan;
+    p->ctx = ctx;
+    try {
+        p->an = analyze(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits, prec);
+        build_plan(p, net->net, max_slices_in_flight);
+    } catch (...) {
+        free_plan_device(p);
+        delete p;
+        throw;
+    }
+    *out = p;
+    API_END
+}
+
+extern "C" int tnc_plan_destroy(tnc_plan *plan) {
+    API_BEGIN
+    if (!plan) return TNC_OK;
+    hipSetDevice(plan->ctx->device);
+    free_plan_device(plan);
+    delete plan;
+    API_END
+}
+
+extern "C" int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats) {
+    API_BEGIN
+    REQUIRE(plan && stats, "NULL argument");
+    fill_stats(plan->an, *stats);
+    stats->slices_in_flight = plan->S;
+    stats->peak_bytes = (double)plan->peak;
+    API_END
+}
+
+extern "C" int tnc_plan_analyze(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs, int32_t n_sliced,
+                                const int32_t *sliced_labels, int32_t n_open, const int32_t *open_qubits,
+                                tnc_precision prec, tnc_plan_stats *stats) {
+    API_BEGIN
+    REQUIRE(net && stats, "NULL argument");
+    REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
+    Analysis an = analyze(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits, prec);
+    fill_stats(an, *stats);
+    stats->slices_in_flight = 0;
+    stats->peak_bytes = (double)plan_memory(an, 1, false);
+    API_END
+}
+
+// ------------------------------------------------------------------ execution
+
+namespace {
+
+struct StepLaunch {
+    const tnc_plan *p;
+    hipStream_t st;
+};
+
+struct StepTimer {
+    hipEvent_t e[3];
+};
+
+// Enqueue the permutes and the GEMM of step s for S slices; with a timer,
+// events bracket the permutes and the GEMM.
+void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = nullptr) {
+    const Analysis &an = p->an;
+    const StepRec &rec = an.steps[s];
+    const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
+    uint8_t *ws = p->ctx->ws;
+    const Dtype dt = an.dt;
+    const int es = elem_bytes(dt);
+    const int Sl = rec.dep ? S_g : 1;
+    const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank(), nz = (int64_t)1 << Z.rank();
+    const void *pa = ws + A.off;
+    const void *pb = ws + B.off;
+    if (tm) HIP_CHECK(hipEventRecord(tm->e[0], st));
+    if (rec.perm_a) {
+        PermuteDesc d = make_permute(rec.a_from, A.labels);
+        int Sa = A.dep ? S_g : 1;
+        launch_permute(dt, ws + A.off, ws + rec.scr_a, d, na, Sa, A.dep ? na : 0, nullptr, A.dep ? na : 0, st);
+        pa = ws + rec.scr_a;
+    }
+    if (rec.perm_b) {
+        PermuteDesc d = make_permute(rec.b_from, B.labels);
+        int Sb = B.dep ? S_g : 1;
+        launch_permute(dt, ws + B.off, ws + rec.scr_b, d, nbb, Sb, B.dep ? nbb : 0, nullptr, B.dep ? nbb : 0, st);
+        pb = ws + rec.scr_b;
+    }
+    GemmShape g{rec.M, rec.N, rec.K, rec.nb, A.dep ? na : 0, B.dep ? nbb : 0, nz, rec.M * rec.K, rec.N * rec.K,
+                rec.M * rec.N};
+    (void)es;
+    ScaleRefs sc{};
+    if (dt != Dtype::C64) {
+        const int S = p->S;
+        sc.maxA = p->d_maxw + (int64_t)rec.a * S;
+        sc.mA = A.dep ? 1 : 0;
+        sc.maxB = p->d_maxw + (int64_t)rec.b * S;
+        sc.mB = B.dep ? 1 : 0;
+        sc.maxC = p->d_maxw + (int64_t)rec.z * S;
+        sc.expA = p->d_expw + (int64_t)rec.a * S;
+        sc.eA = sc.mA;
+        sc.expB = p->d_expw + (int64_t)rec.b * S;
+        sc.eB = sc.mB;
+        sc.expC = p->d_expw + (int64_t)rec.z * S;
+        sc.shift = p->d_shift + (int64_t)rec.z * S;
+        sc.growth = p->d_growth + s;
+        sc.flag = p->d_flags + s;
+    }
+    if (tm) HIP_CHECK(hipEventRecord(tm->e[1], st));
+    launch_gemm(rec.kernel, dt, an.al, pa, pb, ws + Z.off, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+    if (tm) HIP_CHECK(hipEventRecord(tm->e[2], st));
+}
+
+// The whole slice block: invariant phase, then every group of slices.
+void enqueue_block(tnc_plan *p, int64_t nsl, int64_t nbits, hipStream_t st, bool timed) {
+    const Analysis &an = p->an;
+    const int S = p->S;
+    const Dtype dt = an.dt;
+    const int64_t nslots = (int64_t)an.tensors.size() * S;
+    launch_fill_f64(p->d_acc, 0.0, 2 * nbits, st);
+    if (dt != Dtype::C64) launch_fill_u32(p->d_maxw, 0u, nslots, st);
+    launch_gather_leaves_impl(dt, p->n_inv_leaves, p->d_desc, p->d_params, p->d_leafdata, p->ctx->ws, p->d_maxw,
+                              p->d_expw, 0, 1, st);
+    StepTimer tm{};
+    if (timed)
+        for (auto &e : tm.e) HIP_CHECK(hipEventCreate(&e));
+    auto run = [&](int s, int S_g) {
+        enqueue_step(p, s, S_g, st, timed ? &tm : nullptr);
+        if (timed) {
+            HIP_CHECK(hipEventSynchronize(tm.e[2]));
+            float a = 0, b = 0;
+            HIP_CHECK(hipEventElapsedTime(&a, tm.e[0], tm.e[1]));
+            HIP_CHECK(hipEventElapsedTime(&b, tm.e[1], tm.e[2]));
+            p->perm_ms[s] += a;
+            p->step_ms[s] += b;
+            p->step_launches[s] += 1;
+        }
+    };
+    for (int s = 0; s < (int)an.steps.size(); s++)
+        if (!an.steps[s].dep) run(s, 1);
+    const TensorRec &R = an.tensors[an.root];
+    for (int64_t g0 = 0; g0 < nsl; g0 += S) {
+        const int S_g = (int)std::min<int64_t>(S, nsl - g0);
+        if (dt != Dtype::C64 && g0 > 0) {
+            // clear the dependent max words of the previous group
+            for (size_t t = 0; t < an.tensors.size(); t++)
+                if (an.tensors[t].dep) launch_fill_u32(p->d_maxw + (int64_t)t * S, 0u, S, st);
+        }
+        launch_gather_leaves_impl(dt, p->n_dep_leaves, p->d_desc + p->n_inv_leaves, p->d_params, p->d_leafdata,
+                                  p->ctx->ws, p->d_maxw, p->d_expw, (int)g0, S_g, st);
+        for (int s = 0; s < (int)an.steps.size(); s++)
+            if (an.steps[s].dep) run(s, S_g);
+        launch_accumulate(dt, p->ctx->ws + R.off, R.rank(), S_g, (int64_t)1 << R.rank(),
+                          dt == Dtype::C64 ? nullptr : p->d_expw + (int64_t)an.root * S, 1, nbits, p->d_bits, p->d_qob,
+                          p->d_acc, st);
+    }
+    if (timed)
+        for (auto &e : tm.e) hipEventDestroy(e);
+}
+
+}  // namespace
+
+extern "C" int tnc_plan_set_timing(tnc_plan *plan, int32_t on) {
+    API_BEGIN
+    REQUIRE(plan, "plan is NULL");
+    plan->timing = on != 0;
+    API_END
+}
+
+extern "C" int tnc_plan_step_times(const tnc_plan *plan, int32_t n_steps, double *gemm_ms, double *permute_ms,
+                                   int32_t *launches) {
+    API_BEGIN
+    REQUIRE(plan, "plan is NULL");
+    REQUIRE(n_steps >= (int)plan->step_ms.size(), "arrays too small");
+    for (size_t i = 0; i < plan->step_ms.size(); i++) {
+        if (gemm_ms) gemm_ms[i] = plan->step_ms[i];
+        if (permute_ms) permute_ms[i] = plan->perm_ms[i];
+        if (launches) launches[i] = plan->step_launches[i];
+    }
+    API_END
+}
+
+extern "C" int tnc_plan_steps(const tnc_plan *plan, int32_t n_steps, int32_t *log2_mnkb, int32_t *kernel, int32_t *dep,
+                              int32_t *perm_ab, double *flops, double *bytes) {
+    API_BEGIN
+    REQUIRE(plan, "plan is NULL");
+    const auto &st = plan->an.steps;
+    REQUIRE(n_steps >= (int)st.size(), "arrays too small");
+    for (size_t i = 0; i < st.size(); i++) {
+        const StepRec &r = st[i];
+        if (log2_mnkb) {
+            log2_mnkb[4 * i] = (int)r.m.size();
+            log2_mnkb[4 * i + 1] = (int)r.n.size();
+            log2_mnkb[4 * i + 2] = (int)r.k.size();
+            log2_mnkb[4 * i + 3] = (int)r.beta.size();
+        }
+        if (kernel) kernel[i] = r.kernel;
+        if (dep) dep[i] = r.dep ? 1 : 0;
+        if (perm_ab) {
+            perm_ab[2 * i] = r.perm_a ? 1 : 0;
+            perm_ab[2 * i + 1] = r.perm_b ? 1 : 0;
+        }
+        if (flops) flops[i] = r.flops;
+        if (bytes) bytes[i] = r.bytes;
+    }
+    API_END
+}
+
+extern "C" int tnc_execute(tnc_plan *p, int64_t n_bitstrings, const uint64_t *bitstrings, int64_t slice_begin,
+                           int64_t slice_end, double *out_c128, tnc_report *rep) {
+    API_BEGIN
+    REQUIRE(p, "plan is NULL");
+    REQUIRE(n_bitstrings >= 0, "n_bitstrings < 0");
+    REQUIRE(n_bitstrings == 0 || (bitstrings && out_c128), "bitstrings or out_c128 is NULL");
+    const Analysis &an = p->an;
+    const int64_t total = (int64_t)1 << an.n_sliced;
+    REQUIRE(slice_begin >= 0 && slice_begin <= slice_end && slice_end <= total, "slice range out of [0, 2^n_sliced]");
+    tnc_ctx *ctx = p->ctx;
+    HIP_CHECK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (rep) *rep = tnc_report{};
+    const int64_t nsl = slice_end - slice_begin;
+    if (n_bitstrings == 0) return TNC_OK;
+    // closed qubits: values must agree across the request
+    std::vector<int> closed_val(p->n_qubits, 0);
+    for (int q : p->closed_qubits) {
+        int v = (int)((bitstrings[0] >> q) & 1ull);
+        for (int64_t j = 1; j < n_bitstrings; j++)
+            if ((int)((bitstrings[j] >> q) & 1ull) != v)
+                TNC_THROW(TNC_EINVAL, "bitstrings disagree on closed qubit " + std::to_string(q));
+        closed_val[q] = v;
+    }
+    bool desc_dirty = false;
+    for (int i = 0; i < p->nT; i++) {
+        const auto &orig = p->leaf_orig_labels[i];
+        int64_t off = 0;
+        const int ro = (int)orig.size();
+        for (int j = 0; j < ro; j++) {
+            int l = orig[j];
+            if (an.fixed[l] == 1) {
+                int q = an.open_qubit_of_label.size() ? -1 : -1;
+                // find the qubit of this output label
+                for (int qq : p->closed_qubits)
+                    if (p->output_labels[qq] == l) q = qq;
+                if (closed_val[q]) off += (int64_t)1 << (ro - 1 - j);
+            }
+        }
+        if (off != p->closed_state[i]) {
+            p->closed_state[i] = off;
+            p->h_desc[p->desc_of_leaf[i]].closed_off = off;
+            desc_dirty = true;
+        }
+    }
+    if (desc_dirty)
+        HIP_CHECK(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(LeafDesc) * p->h_desc.size(),
+                                 hipMemcpyHostToDevice, st));
+    if (n_bitstrings > p->bits_cap) {
+        if (p->d_bits) hipFree(p->d_bits);
+        if (p->d_acc) hipFree(p->d_acc);
+        p->d_bits = nullptr;
+        p->d_acc = nullptr;
+        for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
+        p->graphs.clear();
+        p->d_bits = dev_alloc<uint64_t>(n_bitstrings);
+        p->d_acc = dev_alloc<double>(2 * n_bitstrings);
+        p->bits_cap = n_bitstrings;
+    }
+    HIP_CHECK(hipMemcpyAsync(p->d_bits, bitstrings, sizeof(uint64_t) * n_bitstrings, hipMemcpyHostToDevice, st));
+    int64_t params[4] = {slice_begin, 0, 0, 0};
+    HIP_CHECK(hipMemcpyAsync(p->d_params, params, sizeof(params), hipMemcpyHostToDevice, st));
+
+    hipEvent_t ev0, ev1;
+    HIP_CHECK(hipEventCreate(&ev0));
+    HIP_CHECK(hipEventCreate(&ev1));
+    int replays = 0, launches = 0;
+    float ms = 0.f;
+    const int ns = (int)an.steps.size();
+    for (;;) {
+        if (p->timing) {
+            std::fill(p->step_ms.begin(), p->step_ms.end(), 0.0);
+            std::fill(p->perm_ms.begin(), p->perm_ms.end(), 0.0);
+            std::fill(p->step_launches.begin(), p->step_launches.end(), 0);
+        }
+        bool graph = p->use_graph && !p->timing;
+        if (graph) {
+            auto key = std::make_tuple(nsl, n_bitstrings, (const void *)p->d_bits);
+            auto it = p->graphs.find(key);
+            if (it == p->graphs.end()) {
+                hipGraph_t gr;
+                HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                try {
+                    enqueue_block(p, nsl, n_bitstrings, st, false);
+                } catch (...) {
+                    hipStreamEndCapture(st, &gr);
+                    if (gr) hipGraphDestroy(gr);
+                    throw;
+                }
+                HIP_CHECK(hipStreamEndCapture(st, &gr));
+                hipGraphExec_t ex;
+                HIP_CHECK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+                hipGraphDestroy(gr);
+                it = p->graphs.emplace(key, ex).first;
+            }
+            HIP_CHECK(hipEventRecord(ev0, st));
+            HIP_CHECK(hipGraphLaunch(it->second, st));
+            HIP_CHECK(hipEventRecord(ev1, st));
+            launches++;
+        } else {
+            HIP_CHECK(hipEventRecord(ev0, st));
+            enqueue_block(p, nsl, n_bitstrings, st, p->timing);
+            HIP_CHECK(hipEventRecord(ev1, st));
+        }
+        HIP_CHECK(hipEventSynchronize(ev1));
+        float t = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&t, ev0, ev1));
+        ms += t;
+        if (an.dt == Dtype::C64) break;
+        std::vector<uint32_t> flags(ns);
+        HIP_CHECK(hipMemcpy(flags.data(), p->d_flags, sizeof(uint32_t) * ns, hipMemcpyDeviceToHost));
+        bool any = false;
+        for (int s = 0; s < ns; s++)
+            if (flags[s]) {
+                any = true;
+                p->h_growth[s] += 4;
+            }
+        if (!any) break;
+        if (replays >= 3) {
+            hipEventDestroy(ev0);
+            hipEventDestroy(ev1);
+            TNC_THROW(TNC_EOVERFLOW, "16-bit range exceeded after 3 rescale replays");
+        }
+        replays++;
+        HIP_CHECK(hipMemcpyAsync(p->d_growth, p->h_growth.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+        launch_fill_u32(p->d_flags, 0u, ns, st);
+    }
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+    HIP_CHECK(hipMemcpyAsync(out_c128, p->d_acc, sizeof(double) * 2 * n_bitstrings, hipMemcpyDefault, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (rep) {
+        double fl = 0;
+        for (auto &s : an.steps) fl += s.dep ? s.flops * (double)nsl : s.flops;
+        rep->seconds = ms * 1e-3;
+        rep->flops = fl;
+        rep->slices = nsl;
+        rep->replays = replays;
+        rep->graph_launches = launches;
+    }
+    API_END
+}

@@ -1,0 +1,63 @@
+// Engine objects behind the C handles.
+#pragma once
+
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+#include "planner.h"
+
+struct tnc_network {
+    tnc::Network net;
+};
+
+namespace tnc {
+struct Mlp;   // learned step-cost model (mlp.hip)
+void mlp_free(Mlp *m);
+}
+
+struct tnc_ctx {
+    int device = 0;
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    uint8_t *small = nullptr;          // 4 KiB of device scratch owned by the context
+    tnc::Mlp *mlp = nullptr;
+};
+
+struct tnc_plan {
+    tnc_ctx *ctx = nullptr;
+    tnc::Analysis an;
+    int S = 1;                         // slices in flight
+    int64_t peak = 0;
+    int nT = 0;                        // input tensors
+    int n_qubits = 0;
+    std::vector<int> output_labels;
+    std::vector<int> closed_qubits;    // qubits whose output label is fixed per call
+    std::vector<std::vector<int>> leaf_orig_labels;   // input labels as given
+    // device buffers owned by the plan
+    void *d_leafdata = nullptr;
+    tnc::LeafDesc *d_desc = nullptr;   // invariant descriptors first, then dependent
+    std::vector<tnc::LeafDesc> h_desc;
+    int n_inv_leaves = 0, n_dep_leaves = 0;
+    std::vector<int> desc_of_leaf;
+    uint32_t *d_maxw = nullptr;
+    double *d_expw = nullptr;
+    int *d_shift = nullptr;
+    int *d_growth = nullptr;
+    uint32_t *d_flags = nullptr;
+    int64_t *d_params = nullptr;
+    uint64_t *d_bits = nullptr;
+    int64_t bits_cap = 0;
+    double *d_acc = nullptr;
+    int *d_qob = nullptr;
+    std::vector<int> h_growth;
+    std::vector<int64_t> closed_state;  // closed_off per leaf last uploaded
+    // graph cache: (slices, bitstrings, bits pointer) -> executable graph
+    std::map<std::tuple<int64_t, int64_t, const void *>, hipGraphExec_t> graphs;
+    bool use_graph = true;
+    bool timing = false;
+    std::vector<double> step_ms, perm_ms;
+    std::vector<int> step_launches;
+};

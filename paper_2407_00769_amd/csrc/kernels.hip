@@ -1,0 +1,286 @@
+// HIP kernels for gfx950: operand permutes, slice selection of the input
+// tensors, batched complex GEMMs (complex64 on FP32 matrix cores; FP16/BF16
+// 4M and 3M on 16-bit matrix cores with FP32 accumulation and a power-of-two
+// output scale), and the FP64 cross-slice amplitude sum.
+//
+// Complex storage: C64 = float2 (re, im); 16-bit forms = one 32-bit word per
+// entry, re in the low half, im in the high half (paper Sec. 3.3: complex-half
+// as a real tensor with a trailing re/im mode).
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "device_util.h"
+
+namespace tnc {
+
+// ===================================================================== small utilities
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill_f64_kernel(double *p, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int grid_for(int64_t n, int threads, int cap = 65536) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+    HIP_CHECK(hipGetLastError());
+}
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ===================================================================== permute (bit permutation)
+//
+// dst[s][j] = src[s * src_slice_stride + slice_off[s] + sum_b bit_b(j) * stride[b]]
+// The destination is written contiguously; reads follow the permutation.
+
+template <typename W>
+__global__ void permute_naive_kernel(const W *__restrict__ src, W *__restrict__ dst, PermuteDesc d,
+                                     int64_t n_out, int64_t src_ss, const int64_t *__restrict__ soff,
+                                     int64_t dst_ss) {
+    const int s = blockIdx.y;
+    const W *sp = src + s * src_ss + (soff ? soff[s] : 0);
+    W *dp = dst + s * dst_ss;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_out;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o = 0;
+        int64_t jj = j;
+        for (int b = 0; b < d.rank; b++) {
+            if (jj & 1) o += d.src_stride[b];
+            jj >>= 1;
+        }
+        dp[j] = sp[o];
+    }
+}
+
+// Tiled variant: the 2^w lowest destination bits and the 2^w lowest source
+// bits form an LDS tile so both the HBM read and the HBM write are contiguous
+// runs of 2^w entries.  Host guarantees: rank >= 2w, the w lowest source bits
+// are destination bits in tb[w..2w) (distinct from the w lowest destination
+// bits), and every remaining destination bit is outside both sets.
+template <typename W, int LW>
+__global__ void __launch_bounds__(256) permute_tiled_kernel(const W *__restrict__ src, W *__restrict__ dst,
+                                                            PermuteDesc d, int64_t n_tiles,
+                                                            int64_t src_ss, const int64_t *__restrict__ soff,
+                                                            int64_t dst_ss, TileBits tb) {
+    constexpr int T = 1 << LW;
+    __shared__ W tile[T][T + 1];
+    const int s = blockIdx.y;
+    const W *sp = src + s * src_ss + (soff ? soff[s] : 0);
+    W *dp = dst + s * dst_ss;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        // destination offset and source offset of the tile's base (bits outside the tile)
+        int64_t dbase = 0, sbase = 0;
+        int64_t tt = t;
+        for (int i = 0; i < tb.n_rest; i++) {
+            int b = tb.rest[i];
+            if (tt & 1) {
+                dbase += (int64_t)1 << b;
+                sbase += d.src_stride[b];
+            }
+            tt >>= 1;
+        }
+        // read: x = source-fast index (dest bits tb.hi[x-bits]), y = dest-fast index
+        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+            int x = e & (T - 1), y = e >> LW;
+            int64_t so = sbase + (int64_t)x;   // the LW lowest source bits, in order
+            for (int i = 0; i < LW; i++)
+                if ((y >> i) & 1) so += d.src_stride[i];
+            tile[y][x] = sp[so];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+            int y = e & (T - 1), x = e >> LW;
+            int64_t dof = dbase + (int64_t)y;
+            for (int i = 0; i < LW; i++)
+                if ((x >> i) & 1) dof += (int64_t)1 << tb.hi[i];
+            dp[dof] = tile[y][x];
+        }
+        __syncthreads();
+    }
+}
+
+void launch_permute(Dtype dt, const void *src, void *dst, const PermuteDesc &d, int64_t n_out, int S,
+                    int64_t src_ss, const int64_t *soff, int64_t dst_ss, hipStream_t st) {
+    if (n_out <= 0 || S <= 0) return;
+    TileBits tb;
+    const int LW = 5;
+    bool tiled = plan_tile_bits(d, LW, tb);
+    if (tiled) {
+        int64_t n_tiles = n_out >> (2 * LW);
+        int g = grid_for(n_tiles, 1, 1 << 20);
+        if (dt == Dtype::C64)
+            hipLaunchKernelGGL((permute_tiled_kernel<uint2, 5>), dim3(g, S), dim3(256), 0, st,
+                               (const uint2 *)src, (uint2 *)dst, d, n_tiles, src_ss, soff, dst_ss, tb);
+        else
+            hipLaunchKernelGGL((permute_tiled_kernel<uint32_t, 5>), dim3(g, S), dim3(256), 0, st,
+                               (const uint32_t *)src, (uint32_t *)dst, d, n_tiles, src_ss, soff, dst_ss, tb);
+    } else {
+        int g = grid_for(n_out, 256, 1 << 20);
+        if (dt == Dtype::C64)
+            hipLaunchKernelGGL((permute_naive_kernel<uint2>), dim3(g, S), dim3(256), 0, st,
+                               (const uint2 *)src, (uint2 *)dst, d, n_out, src_ss, soff, dst_ss);
+        else
+            hipLaunchKernelGGL((permute_naive_kernel<uint32_t>), dim3(g, S), dim3(256), 0, st,
+                               (const uint32_t *)src, (uint32_t *)dst, d, n_out, src_ss, soff, dst_ss);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+// ===================================================================== leaf selection (slicing)
+//
+// One launch gathers every input tensor of a slice group: block (leaf, slice)
+// copies the sub-tensor of leaf i at the fixed label values of slice
+// sigma = sigma0 + s into the arena, in the order its first step wants, and
+// records its largest component (16-bit forms) and a zero exponent.
+
+template <typename W>
+__global__ void gather_leaves_kernel(const LeafDesc *__restrict__ descs, const int64_t *__restrict__ params,
+                                     const W *__restrict__ leafdata, uint8_t *__restrict__ arena,
+                                     uint32_t *__restrict__ maxw, double *__restrict__ expw, int group_base) {
+    const LeafDesc &L = descs[blockIdx.x];
+    const int s = blockIdx.y;
+    if (s >= L.n_slices) return;
+    const int64_t sigma = params[0] + group_base + s;
+    int64_t so = L.src_off + L.closed_off;
+    for (int j = 0; j < L.n_sliced; j++)
+        if ((sigma >> L.slice_bit[j]) & 1) so += L.slice_stride[j];
+    W *dp = (W *)(arena + L.dst_byte_off) + (int64_t)s * L.dst_slice_stride;
+    const int64_t n = (int64_t)1 << L.rank;
+    float mx = 0.f;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        int64_t o = so;
+        for (int b = 0; b < L.rank; b++)
+            if ((j >> b) & 1) o += L.stride[b];
+        W v = leafdata[o];
+        dp[j] = v;
+        mx = fmaxf(mx, word_absmax(v));
+    }
+    if (maxw) {
+        mx = block_max(mx);
+        if (threadIdx.x == 0) {
+            atomicMax(&maxw[L.max_slot + s * L.slot_stride], __float_as_uint(mx));
+            expw[L.max_slot + s * L.slot_stride] = 0.0;
+        }
+    }
+}
+
+void launch_gather_leaves_impl(Dtype dt, int n_leaves, const LeafDesc *d_desc, const int64_t *d_params,
+                               const void *leafdata, uint8_t *arena, uint32_t *maxw, double *expw,
+                               int group_base, int S, hipStream_t st) {
+    if (n_leaves <= 0) return;
+    if (dt == Dtype::C64)
+        hipLaunchKernelGGL((gather_leaves_kernel<uint2>), dim3(n_leaves, S), dim3(64), 0, st, d_desc, d_params,
+                           (const uint2 *)leafdata, arena, (uint32_t *)nullptr, (double *)nullptr, group_base);
+    else if (dt == Dtype::F16)
+        hipLaunchKernelGGL((gather_leaves_kernel<HalfWord>), dim3(n_leaves, S), dim3(64), 0, st, d_desc,
+                           d_params, (const HalfWord *)leafdata, arena, maxw, expw, group_base);
+    else
+        hipLaunchKernelGGL((gather_leaves_kernel<Bf16Word>), dim3(n_leaves, S), dim3(64), 0, st, d_desc,
+                           d_params, (const Bf16Word *)leafdata, arena, maxw, expw, group_base);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ===================================================================== FP64 cross-slice sum
+//
+// acc[j] += 2^exp[s] * R[s][idx(x_j)] for s = 0..S-1 in order (deterministic).
+// idx(x) takes bit b from qubit qubit_of_bit[b] of the bitstring.
+
+template <typename W>
+__global__ void accumulate_kernel(const W *__restrict__ R, int rank, int S, int64_t ss,
+                                  const double *__restrict__ expR, int es, int64_t nbits,
+                                  const uint64_t *__restrict__ bits, const int *__restrict__ qob,
+                                  double *__restrict__ acc) {
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= nbits) return;
+    uint64_t x = bits[j];
+    int64_t idx = 0;
+    for (int b = 0; b < rank; b++) idx |= (int64_t)((x >> qob[b]) & 1ull) << b;
+    double re = acc[2 * j], im = acc[2 * j + 1];
+    for (int s = 0; s < S; s++) {
+        double2 v = word_to_double2(R[s * ss + idx]);
+        double e = expR ? expR[s * es] : 0.0;
+        re += ldexp(v.x, (int)e);
+        im += ldexp(v.y, (int)e);
+    }
+    acc[2 * j] = re;
+    acc[2 * j + 1] = im;
+}
+
+void launch_accumulate(Dtype dt, const void *R, int rank, int S, int64_t ss, const double *expR, int es,
+                       int64_t nbits, const uint64_t *d_bits, const int *d_qob, double *acc, hipStream_t st) {
+    if (nbits <= 0 || S <= 0) return;
+    int g = (int)((nbits + 255) / 256);
+    if (dt == Dtype::C64)
+        hipLaunchKernelGGL((accumulate_kernel<uint2>), dim3(g), dim3(256), 0, st, (const uint2 *)R, rank, S, ss,
+                           (const double *)nullptr, es, nbits, d_bits, d_qob, acc);
+    else if (dt == Dtype::F16)
+        hipLaunchKernelGGL((accumulate_kernel<HalfWord>), dim3(g), dim3(256), 0, st, (const HalfWord *)R, rank, S,
+                           ss, expR, es, nbits, d_bits, d_qob, acc);
+    else
+        hipLaunchKernelGGL((accumulate_kernel<Bf16Word>), dim3(g), dim3(256), 0, st, (const Bf16Word *)R, rank, S,
+                           ss, expR, es, nbits, d_bits, d_qob, acc);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ===================================================================== tensor max (for one-off contractions)
+
+template <typename W>
+__global__ void tensor_max_kernel(const W *__restrict__ x, int64_t n, int64_t ss, uint32_t *__restrict__ out) {
+    const int s = blockIdx.y;
+    float mx = 0.f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        mx = fmaxf(mx, word_absmax(x[s * ss + i]));
+    mx = block_max(mx);
+    if (threadIdx.x == 0) atomicMax(&out[s], __float_as_uint(mx));
+}
+
+void launch_tensor_max(Dtype dt, const void *x, int64_t n, int S, int64_t ss, uint32_t *out, hipStream_t st) {
+    int g = grid_for(n, 256, 4096);
+    if (dt == Dtype::C64)
+        hipLaunchKernelGGL((tensor_max_kernel<uint2>), dim3(g, S), dim3(256), 0, st, (const uint2 *)x, n, ss, out);
+    else if (dt == Dtype::F16)
+        hipLaunchKernelGGL((tensor_max_kernel<HalfWord>), dim3(g, S), dim3(256), 0, st, (const HalfWord *)x, n, ss, out);
+    else
+        hipLaunchKernelGGL((tensor_max_kernel<Bf16Word>), dim3(g, S), dim3(256), 0, st, (const Bf16Word *)x, n, ss, out);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ===================================================================== input conversion
+// complex128 (interleaved doubles) -> storage words, round to nearest even.
+template <typename W>
+__global__ void convert_c128_kernel(const double *__restrict__ src, int64_t n, W *__restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = Pack<W>::make((float)src[2 * i], (float)src[2 * i + 1]);
+}
+
+void launch_convert_c128(const double *src, int64_t n, Dtype dt, void *dst, hipStream_t st) {
+    if (n <= 0) return;
+    int g = grid_for(n, 256, 4096);
+    if (dt == Dtype::C64)
+        hipLaunchKernelGGL((convert_c128_kernel<uint2>), dim3(g), dim3(256), 0, st, src, n, (uint2 *)dst);
+    else if (dt == Dtype::F16)
+        hipLaunchKernelGGL((convert_c128_kernel<HalfWord>), dim3(g), dim3(256), 0, st, src, n, (HalfWord *)dst);
+    else
+        hipLaunchKernelGGL((convert_c128_kernel<Bf16Word>), dim3(g), dim3(256), 0, st, src, n, (Bf16Word *)dst);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace tnc

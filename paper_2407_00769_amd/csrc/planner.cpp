@@ -1,0 +1,434 @@
+// Host planner.  For every pairwise step of the path it classifies labels
+// (paper Sec. 3.3: a pairwise einsum is a pure GEMM when the reduced labels
+// are exactly the labels both operands share and the result keeps the rest):
+//   batch = in A, in B, kept;   m = A only, kept;   n = B only, kept;
+//   k = in A and B, not kept (summed).
+// It then picks storage orders so operands can be fed to the GEMM as
+// [batch][m][k] and [batch][n][k] without a permute where possible, and
+// lays out the arena.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "planner.h"
+
+namespace tnc {
+
+static std::string lbl(int l) { return std::to_string(l); }
+
+PermuteDesc make_permute(const std::vector<int> &from, const std::vector<int> &to) {
+    PermuteDesc d{};
+    const int r = (int)to.size();
+    if (r > kMaxRank) TNC_THROW(TNC_EUNSUPPORTED, "tensor rank above 48");
+    d.rank = r;
+    const int rf = (int)from.size();
+    for (int b = 0; b < r; b++) {
+        int label = to[r - 1 - b];
+        auto it = std::find(from.begin(), from.end(), label);
+        if (it == from.end()) TNC_THROW(TNC_EINVAL, "internal: permute label missing");
+        int pos = rf - 1 - (int)(it - from.begin());
+        d.src_stride[b] = (int64_t)1 << pos;
+    }
+    return d;
+}
+
+bool plan_tile_bits(const PermuteDesc &d, int lw, TileBits &tb) {
+    const int r = d.rank;
+    if (r < 2 * lw) return false;
+    // identity on the low bits: the plain kernel is already coalesced
+    int run = 0;
+    while (run < r && d.src_stride[run] == ((int64_t)1 << run)) run++;
+    if (run >= 4) return false;
+    bool in_tile[kMaxRank] = {false};
+    for (int b = 0; b < lw; b++) in_tile[b] = true;
+    for (int i = 0; i < lw; i++) {
+        int found = -1;
+        for (int b = 0; b < r; b++)
+            if (d.src_stride[b] == ((int64_t)1 << i)) found = b;
+        if (found < 0 || found < lw) return false;   // a low source bit is fixed or is also a low dest bit
+        tb.hi[i] = found;
+        in_tile[found] = true;
+    }
+    tb.n_rest = 0;
+    for (int b = 0; b < r; b++)
+        if (!in_tile[b]) tb.rest[tb.n_rest++] = b;
+    return true;
+}
+
+// Does `order` read as [g0-block][g1-block][g2-block] (MSB first)?
+static bool has_pattern(const std::vector<int> &order, const std::vector<int> &grp /* label -> group */,
+                        const std::vector<int> &sizes) {
+    int pos = 0;
+    for (int gi = 0; gi < 3; gi++) {
+        for (int c = 0; c < sizes[gi]; c++, pos++) {
+            if (pos >= (int)order.size() || grp[order[pos]] != gi) return false;
+        }
+    }
+    return pos == (int)order.size();
+}
+
+static std::vector<int> extract(const std::vector<int> &order, const std::vector<int> &grp, int gi) {
+    std::vector<int> r;
+    for (int l : order)
+        if (grp[l] == gi) r.push_back(l);
+    return r;
+}
+
+int choose_kernel(Dtype dt, Algo al, const GemmShape &g) {
+    if (al == Algo::M4) {
+        if (g.N >= 64 && g.M >= 128 && gemm_supported(K_MFMA_L, dt, al, g)) return K_MFMA_L;
+        if (g.N >= 32 && g.M >= 128 && gemm_supported(K_MFMA_M, dt, al, g)) return K_MFMA_M;
+        if (g.N >= 16 && g.M >= 256 && gemm_supported(K_MFMA_W, dt, al, g)) return K_MFMA_W;
+        if (gemm_supported(K_MFMA_S, dt, al, g)) return K_MFMA_S;
+    }
+    if (gemm_supported(K_SKINNY_N, dt, al, g)) return K_SKINNY_N;
+    return K_NAIVE;
+}
+
+Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_sliced, const int32_t *sliced,
+                 int n_open, const int32_t *open_q, tnc_precision prec) {
+    Analysis an;
+    an.dt = dtype_of(prec);
+    an.al = algo_of(prec);
+    if ((int)prec < 0 || (int)prec > 4) TNC_THROW(TNC_EINVAL, "unknown precision");
+    if (an.dt == Dtype::C64 && an.al == Algo::M3) TNC_THROW(TNC_EINVAL, "3M needs 16-bit storage");
+    const int nT = net.n_tensors;
+    const int L = net.n_labels;
+    if (n_steps != nT - 1) TNC_THROW(TNC_EINVAL, "path must have n_tensors - 1 steps");
+    if (n_sliced < 0 || n_sliced > 62) TNC_THROW(TNC_EINVAL, "n_sliced out of range");
+    if (n_open < 0 || n_open > net.n_qubits) TNC_THROW(TNC_EINVAL, "n_open out of range");
+
+    an.fixed.assign(L, -1);
+    an.slice_bit.assign(L, -1);
+    an.open_qubit_of_label.assign(L, -1);
+    std::vector<int> is_output(L, -1);
+    for (int q = 0; q < net.n_qubits; q++) is_output[net.output_labels[q]] = q;
+    std::vector<char> open(net.n_qubits, 0);
+    for (int i = 0; i < n_open; i++) {
+        int q = open_q[i];
+        if (q < 0 || q >= net.n_qubits) TNC_THROW(TNC_EINVAL, "open qubit out of range");
+        if (open[q]) TNC_THROW(TNC_EINVAL, "open qubit listed twice");
+        open[q] = 1;
+        an.open_qubit_of_label[net.output_labels[q]] = q;
+    }
+    for (int q = 0; q < net.n_qubits; q++)
+        if (!open[q]) an.fixed[net.output_labels[q]] = 1;
+    for (int j = 0; j < n_sliced; j++) {
+        int l = sliced[j];
+        if (l < 0 || l >= L) TNC_THROW(TNC_EINVAL, "sliced label " + lbl(l) + " not in the network");
+        if (is_output[l] >= 0) TNC_THROW(TNC_EINVAL, "sliced label " + lbl(l) + " is an output label");
+        if (an.fixed[l] == 0) TNC_THROW(TNC_EINVAL, "sliced label " + lbl(l) + " listed twice");
+        an.fixed[l] = 0;
+        an.slice_bit[l] = j;
+    }
+    an.n_sliced = n_sliced;
+
+    // input tensors with the fixed labels removed
+    std::vector<int> needed(L, 0);
+    an.tensors.resize(2 * nT - 1);
+    for (int i = 0; i < nT; i++) {
+        TensorRec &t = an.tensors[i];
+        t.leaf = true;
+        for (int l : net.labels[i]) {
+            if (an.fixed[l] >= 0) {
+                if (an.fixed[l] == 0) t.dep = true;
+                continue;
+            }
+            t.labels.push_back(l);
+            needed[l]++;
+        }
+        if (t.rank() > kMaxLeafRank) TNC_THROW(TNC_EUNSUPPORTED, "input tensor rank above 16 after slicing");
+    }
+    for (int q = 0; q < net.n_qubits; q++)
+        if (open[q]) needed[net.output_labels[q]]++;
+    if (n_sliced == 0)
+        for (int i = 0; i < nT; i++) an.tensors[i].dep = true;
+
+    // walk the path: label groups, dependence, consumers
+    std::vector<char> alive(2 * nT - 1, 0);
+    for (int i = 0; i < nT; i++) alive[i] = 1;
+    std::vector<int> grp(L, -1);
+    an.steps.resize(n_steps);
+    for (int s = 0; s < n_steps; s++) {
+        int x = ssa[2 * s], y = ssa[2 * s + 1];
+        int z = nT + s;
+        if (x < 0 || y < 0 || x >= z || y >= z || x == y) TNC_THROW(TNC_EINVAL, "path step " + lbl(s) + " has an invalid operand");
+        if (!alive[x] || !alive[y]) TNC_THROW(TNC_EINVAL, "path step " + lbl(s) + " uses a tensor twice");
+        alive[x] = alive[y] = 0;
+        alive[z] = 1;
+        StepRec &st = an.steps[s];
+        st.x = x;
+        st.y = y;
+        st.z = z;
+        TensorRec &X = an.tensors[x], &Y = an.tensors[y], &Z = an.tensors[z];
+        X.consumer = s;
+        Y.consumer = s;
+        Z.producer = s;
+        Z.dep = X.dep || Y.dep;
+        st.dep = Z.dep;
+        std::vector<char> inx(L, 0), iny(L, 0);
+        for (int l : X.labels) inx[l] = 1;
+        for (int l : Y.labels) iny[l] = 1;
+        std::vector<int> uni;
+        for (int l : X.labels) uni.push_back(l);
+        for (int l : Y.labels)
+            if (!inx[l]) uni.push_back(l);
+        for (int l : uni) {
+            int after = needed[l] - inx[l] - iny[l];
+            bool keep = after > 0;
+            needed[l] = after + (keep ? 1 : 0);
+            if (keep) Z.labels.push_back(l);   // provisional order; fixed by the layout pass
+            if (inx[l] && iny[l])
+                (keep ? st.beta : st.k).push_back(l);
+            else if (inx[l]) {
+                if (!keep) TNC_THROW(TNC_EUNSUPPORTED, "label " + lbl(l) + " is summed inside one tensor");
+                st.m.push_back(l);
+            } else {
+                if (!keep) TNC_THROW(TNC_EUNSUPPORTED, "label " + lbl(l) + " is summed inside one tensor");
+                st.n.push_back(l);
+            }
+        }
+        // A = operand with the larger free part (it becomes the GEMM rows)
+        std::vector<int> fx = st.m, fy = st.n;
+        bool swap = fy.size() > fx.size() || (fy.size() == fx.size() && Y.rank() > X.rank());
+        st.a = swap ? y : x;
+        st.b = swap ? x : y;
+        if (swap) std::swap(st.m, st.n);
+        if (Z.rank() > kMaxRank) TNC_THROW(TNC_EUNSUPPORTED, "intermediate rank above 48");
+    }
+    an.root = 2 * nT - 2;
+    if (nT == 1) TNC_THROW(TNC_EUNSUPPORTED, "a network of one tensor has nothing to contract");
+    // the root must hold exactly the open output labels
+    {
+        const TensorRec &R = an.tensors[an.root];
+        int cnt = 0;
+        for (int l : R.labels) {
+            if (an.open_qubit_of_label[l] < 0) TNC_THROW(TNC_EINVAL, "label " + lbl(l) + " survives the path but is not open");
+            cnt++;
+        }
+        if (cnt != n_open) TNC_THROW(TNC_EINVAL, "an open output label never reaches the root");
+    }
+
+    // layout pass: storage orders and permutes
+    const int es = elem_bytes(an.dt);
+    for (int s = 0; s < n_steps; s++) {
+        StepRec &st = an.steps[s];
+        TensorRec &A = an.tensors[st.a], &B = an.tensors[st.b], &Z = an.tensors[st.z];
+        // consumer preference of Z's labels: 0 batch, 1 free, 2 contracted there
+        std::vector<int> pref(L, 1);
+        if (Z.consumer >= 0) {
+            const StepRec &c = an.steps[Z.consumer];
+            for (int l : c.beta) pref[l] = 0;
+            for (int l : c.k) pref[l] = 2;
+        }
+        auto by_pref = [&](std::vector<int> v) {
+            std::stable_sort(v.begin(), v.end(), [&](int p, int q) { return pref[p] < pref[q]; });
+            return v;
+        };
+        // group ids for A: 0 batch, 1 m, 2 k ; for B: 0 batch, 1 n, 2 k
+        for (int l : st.beta) grp[l] = 0;
+        for (int l : st.m) grp[l] = 1;
+        for (int l : st.n) grp[l] = 1;
+        for (int l : st.k) grp[l] = 2;
+        std::vector<int> sa = {(int)st.beta.size(), (int)st.m.size(), (int)st.k.size()};
+        std::vector<int> sb = {(int)st.beta.size(), (int)st.n.size(), (int)st.k.size()};
+        bool a_ok = !A.leaf && has_pattern(A.labels, grp, sa);
+        bool b_ok = !B.leaf && has_pattern(B.labels, grp, sb);
+        // the batch and k orders must agree between A and B; take them from an
+        // operand that keeps its layout, preferring the larger one
+        std::vector<int> beta_o, k_o;
+        const double szA = std::ldexp(1.0, A.rank()), szB = std::ldexp(1.0, B.rank());
+        auto cost_with = [&](const std::vector<int> &bo, const std::vector<int> &ko) {
+            double c = 0;
+            if (!A.leaf && !(a_ok && extract(A.labels, grp, 0) == bo && extract(A.labels, grp, 2) == ko)) c += szA;
+            if (!B.leaf && !(b_ok && extract(B.labels, grp, 0) == bo && extract(B.labels, grp, 2) == ko)) c += szB;
+            return c;
+        };
+        std::vector<std::pair<std::vector<int>, std::vector<int>>> cands;
+        if (a_ok) cands.push_back({extract(A.labels, grp, 0), extract(A.labels, grp, 2)});
+        if (b_ok) cands.push_back({extract(B.labels, grp, 0), extract(B.labels, grp, 2)});
+        if (cands.empty()) {
+            std::vector<int> bo = extract(A.labels, grp, 0), ko = extract(A.labels, grp, 2);
+            if (A.leaf && !B.leaf) {
+                bo = extract(B.labels, grp, 0);
+                ko = extract(B.labels, grp, 2);
+            }
+            cands.push_back({bo, ko});
+        }
+        double best = 1e300;
+        for (auto &c : cands) {
+            double v = cost_with(c.first, c.second);
+            if (v < best) {
+                best = v;
+                beta_o = c.first;
+                k_o = c.second;
+            }
+        }
+        // A: keep, or reorder to [beta][m (consumer order)][k]
+        std::vector<int> m_o, n_o;
+        if (a_ok && extract(A.labels, grp, 0) == beta_o && extract(A.labels, grp, 2) == k_o) {
+            m_o = extract(A.labels, grp, 1);
+        } else {
+            m_o = by_pref(extract(A.labels, grp, 1));
+            std::vector<int> want = beta_o;
+            want.insert(want.end(), m_o.begin(), m_o.end());
+            want.insert(want.end(), k_o.begin(), k_o.end());
+            if (A.leaf) {
+                A.labels = want;
+            } else {
+                st.perm_a = true;
+                st.a_from = A.labels;
+                A.labels = want;   // the permuted copy is what the GEMM reads
+            }
+        }
+        if (b_ok && extract(B.labels, grp, 0) == beta_o && extract(B.labels, grp, 2) == k_o) {
+            n_o = extract(B.labels, grp, 1);
+        } else {
+            n_o = by_pref(extract(B.labels, grp, 1));
+            std::vector<int> want = beta_o;
+            want.insert(want.end(), n_o.begin(), n_o.end());
+            want.insert(want.end(), k_o.begin(), k_o.end());
+            if (B.leaf) {
+                B.labels = want;
+            } else {
+                st.perm_b = true;
+                st.b_from = B.labels;
+                B.labels = want;
+            }
+        }
+        st.beta = beta_o;
+        st.m = m_o;
+        st.n = n_o;
+        st.k = k_o;
+        Z.labels = beta_o;
+        Z.labels.insert(Z.labels.end(), m_o.begin(), m_o.end());
+        Z.labels.insert(Z.labels.end(), n_o.begin(), n_o.end());
+        st.nb = (int64_t)1 << st.beta.size();
+        st.M = (int64_t)1 << st.m.size();
+        st.N = (int64_t)1 << st.n.size();
+        st.K = (int64_t)1 << st.k.size();
+        st.flops = 8.0 * (double)st.nb * (double)st.M * (double)st.N * (double)st.K;
+        st.bytes = es * (std::ldexp(1.0, A.rank()) + std::ldexp(1.0, B.rank()) + std::ldexp(1.0, Z.rank()));
+        st.perm_bytes = (st.perm_a ? 2.0 * es * szA : 0.0) + (st.perm_b ? 2.0 * es * szB : 0.0);
+        GemmShape g{st.M, st.N, st.K, st.nb, 0, 0, 0, st.M * st.K, st.N * st.K, st.M * st.N};
+        st.kernel = choose_kernel(an.dt, an.al, g);
+        for (int l : st.beta) grp[l] = -1;
+        for (int l : st.m) grp[l] = -1;
+        for (int l : st.n) grp[l] = -1;
+        for (int l : st.k) grp[l] = -1;
+        an.max_rank = std::max({an.max_rank, A.rank(), B.rank(), Z.rank()});
+    }
+    return an;
+}
+
+// ------------------------------------------------------------------ arena
+
+namespace {
+struct Arena {
+    std::map<int64_t, int64_t> free_;   // offset -> size
+    int64_t top = 0, peak = 0;
+    static int64_t align(int64_t v) { return (v + 255) & ~(int64_t)255; }
+    int64_t alloc(int64_t bytes) {
+        bytes = align(std::max<int64_t>(bytes, 1));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                int64_t off = it->first, rem = it->second - bytes;
+                free_.erase(it);
+                if (rem > 0) free_[off + bytes] = rem;
+                return off;
+            }
+        }
+        int64_t off = top;
+        top += bytes;
+        peak = std::max(peak, top);
+        return off;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = align(std::max<int64_t>(bytes, 1));
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+                it = pv;
+            }
+        }
+        if (it->first + it->second == top) {
+            top = it->first;
+            free_.erase(it);
+        }
+    }
+};
+}  // namespace
+
+int64_t plan_memory(Analysis &an, int S, bool assign) {
+    const int es = elem_bytes(an.dt);
+    Arena ar;
+    auto bytes_of = [&](const TensorRec &t) {
+        return (int64_t)es * ((int64_t)1 << t.rank()) * (t.dep ? S : 1);
+    };
+    std::vector<int64_t> off(an.tensors.size(), -1);
+    const int nT = (int)(an.tensors.size() + 1) / 2;
+    // invariant phase
+    for (int i = 0; i < nT; i++)
+        if (!an.tensors[i].dep) off[i] = ar.alloc(bytes_of(an.tensors[i]));
+    std::vector<int64_t> scr_a(an.steps.size(), -1), scr_b(an.steps.size(), -1);
+    auto run_step = [&](int s) {
+        StepRec &st = an.steps[s];
+        const TensorRec &A = an.tensors[st.a], &B = an.tensors[st.b], &Z = an.tensors[st.z];
+        // operands of a dependent step that are invariant keep a single copy
+        if (st.perm_a) scr_a[s] = ar.alloc(bytes_of(A));
+        if (st.perm_b) scr_b[s] = ar.alloc(bytes_of(B));
+        off[st.z] = ar.alloc(bytes_of(Z));
+        if (st.perm_a) ar.release(scr_a[s], bytes_of(A));
+        if (st.perm_b) ar.release(scr_b[s], bytes_of(B));
+        for (int t : {st.a, st.b}) {
+            const TensorRec &T = an.tensors[t];
+            if (T.dep == st.dep) ar.release(off[t], bytes_of(T));   // consumed
+        }
+    };
+    for (int s = 0; s < (int)an.steps.size(); s++)
+        if (!an.steps[s].dep) run_step(s);
+    // dependent phase (one slice group)
+    for (int i = 0; i < nT; i++)
+        if (an.tensors[i].dep) off[i] = ar.alloc(bytes_of(an.tensors[i]));
+    for (int s = 0; s < (int)an.steps.size(); s++)
+        if (an.steps[s].dep) run_step(s);
+    if (assign) {
+        for (size_t i = 0; i < an.tensors.size(); i++) an.tensors[i].off = off[i];
+        for (size_t s = 0; s < an.steps.size(); s++) {
+            an.steps[s].scr_a = scr_a[s];
+            an.steps[s].scr_b = scr_b[s];
+        }
+    }
+    return ar.peak;
+}
+
+void fill_stats(const Analysis &an, tnc_plan_stats &st) {
+    st = tnc_plan_stats{};
+    st.n_steps = (int)an.steps.size();
+    st.n_sliced = an.n_sliced;
+    st.max_rank = an.max_rank;
+    st.out_rank = an.tensors[an.root].rank();
+    double pe = 0;
+    for (auto &t : an.tensors) pe = std::max(pe, std::ldexp(1.0, t.rank()));
+    st.peak_elems_per_slice = pe;
+    for (auto &s : an.steps) {
+        if (s.dep) {
+            st.n_dep_steps++;
+            st.flops_per_slice += s.flops;
+            st.bytes_per_slice += s.bytes + s.perm_bytes;
+            st.permute_bytes_per_slice += s.perm_bytes;
+        } else {
+            st.flops_invariant += s.flops;
+        }
+    }
+}
+
+}  // namespace tnc

@@ -1,0 +1,66 @@
+// Host planner: turns (network, path, sliced labels, open qubits) into the
+// steps one slice runs, the memory layout of every tensor, and the arena.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "common.h"
+
+namespace tnc {
+
+struct TensorRec {
+    std::vector<int> labels;    // storage order, first = slowest
+    bool dep = false;           // depends on the slice id
+    bool leaf = false;
+    int producer = -1;          // step index, or -1 for an input tensor
+    int consumer = -1;          // step index, or -1 for the root
+    int64_t off = -1;           // arena byte offset (slice 0)
+    int rank() const { return (int)labels.size(); }
+};
+
+struct StepRec {
+    int x = -1, y = -1, z = -1;       // operand and result tensor ids (SSA)
+    int a = -1, b = -1;               // tensor ids used as A (large side) and B
+    std::vector<int> beta, m, n, k;   // label groups, each in storage order
+    bool perm_a = false, perm_b = false;
+    int64_t scr_a = -1, scr_b = -1;   // arena offsets of the permuted operands
+    std::vector<int> a_from, b_from;  // operand orders before the permute
+    int64_t M = 1, N = 1, K = 1, nb = 1;
+    bool dep = false;
+    int kernel = K_NAIVE;
+    double flops = 0;                 // per slice (or once, if invariant)
+    double bytes = 0;                 // GEMM bytes per slice
+    double perm_bytes = 0;            // permute bytes per slice
+};
+
+struct Analysis {
+    std::vector<TensorRec> tensors;   // leaves 0..n-1, then step results
+    std::vector<StepRec> steps;
+    std::vector<int> fixed;           // per label: -1 free, 0 sliced, 1 closed output
+    std::vector<int> slice_bit;       // per label: bit of the slice id (sliced labels)
+    std::vector<int> open_qubit_of_label;
+    int root = -1;
+    int n_sliced = 0;
+    int max_rank = 0;
+    Dtype dt = Dtype::C64;
+    Algo al = Algo::M4;
+};
+
+// Validate and analyse; throws tnc::Error.
+Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_sliced, const int32_t *sliced,
+                 int n_open, const int32_t *open_q, tnc_precision prec);
+
+// Byte offsets of every tensor and scratch buffer for S slices in flight;
+// returns the arena peak in bytes.
+int64_t plan_memory(Analysis &an, int S, bool assign);
+
+// Default kernel choice for a step shape.
+int choose_kernel(Dtype dt, Algo al, const GemmShape &g);
+
+PermuteDesc make_permute(const std::vector<int> &from, const std::vector<int> &to);
+
+void fill_stats(const Analysis &an, tnc_plan_stats &st);
+
+}  // namespace tnc

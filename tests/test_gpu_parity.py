@@ -1,0 +1,244 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle (through the C-ABI).
+
+* Single contractions (tnc_contract) against oracle.pairwise on the exact
+  stored inputs, for every kernel variant and precision, with an elementwise
+  error bound from FP32 accumulation plus one rounding of the output.
+* The paper's worked complex-half example, exactly.
+* Whole circuits (tnc_execute) against the state-vector oracle: complex64 to
+  fidelity >= 1 - 1e-8, 16-bit forms to >= 0.99 (FP16 expected >= 0.999).
+* Slicing: the sum over all slices equals the state vector; a partial block
+  equals the sum of projected state vectors; disjoint ranges add up; two runs
+  are bit-identical; the graph launch equals step-by-step launches.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import workloads  # noqa: E402
+from oracle import metrics, pairwise, statevector  # noqa: E402
+
+from gpu_util import empty_storage, from_storage, to_storage  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_00769_amd import _tnc
+    return _tnc
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    ws = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
+    st = torch.cuda.Stream()
+    c = T.tnc_create(0, ws, stream=st)
+    yield c
+    T.tnc_destroy(c)
+    torch.cuda.synchronize()
+    del ws
+
+
+PRECS = ["c64", "f16_4m", "f16_3m", "bf16_4m", "bf16_3m"]
+U = {"c64": 2.0 ** -24, "f16_4m": 2.0 ** -11, "f16_3m": 2.0 ** -11, "bf16_4m": 2.0 ** -8, "bf16_3m": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16_4m", "bf16_4m", "f16_3m"])
+def test_worked_example(T, ctx, prec):
+    g = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    a = np.array([complex(*p) for p in g["A"]])
+    b = np.array([complex(*p) for p in g["B"]]).reshape(())
+    A, _ = to_storage(a, prec)
+    B, _ = to_storage(b.reshape(1), prec)
+    C = empty_storage((2,), prec)
+    T.tnc_contract(ctx, prec, A, [7], B, [], C, [7], scale_log2=0)
+    got = from_storage(C, prec)
+    want = np.array([complex(*p) for p in g["C"]])
+    np.testing.assert_array_equal(got, want)
+
+
+def _random_case(rng, nb, m, n, k):
+    labels = list(range(nb + m + n + k))
+    rng.shuffle(labels)
+    beta, ml, nl, kl = labels[:nb], labels[nb:nb + m], labels[nb + m:nb + m + n], labels[nb + m + n:]
+    al = beta + ml + kl
+    bl = beta + nl + kl
+    cl = beta + ml + nl
+    for v in (al, bl, cl):
+        rng.shuffle(v)
+    a = (rng.normal(size=2 ** len(al)) + 1j * rng.normal(size=2 ** len(al))) / np.sqrt(2 * 2 ** k)
+    b = (rng.normal(size=2 ** len(bl)) + 1j * rng.normal(size=2 ** len(bl))) / np.sqrt(2)
+    return al, bl, cl, a, b
+
+
+def _check_contract(T, ctx, prec, nb, m, n, k, seed, scale_log2=0):
+    rng = np.random.default_rng(seed)
+    al, bl, cl, a, b = _random_case(rng, nb, m, n, k)
+    A, av = to_storage(a, prec)
+    B, bv = to_storage(b, prec)
+    C = empty_storage((2 ** len(cl),), prec)
+    T.tnc_contract(ctx, prec, A, al, B, bl, C, cl, scale_log2=scale_log2)
+    got = from_storage(C, prec, scale_log2).reshape((2,) * len(cl))
+    ref = pairwise.contract_pair(av.reshape((2,) * len(al)), al, bv.reshape((2,) * len(bl)), bl, cl)
+    mag = pairwise.contract_pair(np.abs(av).reshape((2,) * len(al)), al, np.abs(bv).reshape((2,) * len(bl)), bl, cl)
+    K = 2 ** k
+    u = U[prec]
+    # FP32 accumulation over 2K real terms, plus one rounding of the stored result;
+    # 3M adds the rounding of the operand sums and cancellation (Higham's bound)
+    acc_u = 2.0 ** -24
+    bound = 4 * K * acc_u * np.abs(mag) + u * np.abs(ref) * 1.01 + 1e-30
+    if prec.endswith("3m"):
+        bound = bound + 6 * u * np.abs(mag)
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), (prec, float(np.max(err / bound)))
+    return got, ref
+
+
+KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5}
+SHAPES = [  # nb, m, n, k  (log2)
+    (0, 9, 6, 5), (1, 8, 5, 3), (0, 10, 4, 6), (2, 7, 7, 4), (0, 8, 0, 2), (0, 6, 3, 0), (0, 12, 5, 7),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kname", list(KERNELS))
+def test_contract_kernels(T, ctx, prec, kname, monkeypatch):
+    monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
+    for i, (nb, m, n, k) in enumerate(SHAPES):
+        _check_contract(T, ctx, prec, nb, m, n, k, seed=100 + i)
+
+
+@pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m", "f16_3m"])
+def test_power_of_two_scale_is_exact(T, ctx, prec):
+    # storing C * 2^-s is exact while the stored value stays a normal number:
+    # those entries agree bit for bit after undoing s (subnormals lose bits)
+    g0, _ = _check_contract(T, ctx, prec, 0, 9, 5, 5, seed=7, scale_log2=0)
+    g1, _ = _check_contract(T, ctx, prec, 0, 9, 5, 5, seed=7, scale_log2=3)
+    g2, _ = _check_contract(T, ctx, prec, 0, 9, 5, 5, seed=7, scale_log2=-4)
+    def normal(g, shift):
+        tiny = 2.0 ** (-14 + shift) if prec.startswith("f16") else 1e-30
+        ok = (np.abs(g.real) >= tiny) | (g.real == 0)
+        return ok & ((np.abs(g.imag) >= tiny) | (g.imag == 0))
+    n1, n0 = normal(g0, 3), normal(g0, 0)
+    assert n1.mean() > 0.99
+    np.testing.assert_array_equal(g0[n1], g1[n1])
+    np.testing.assert_array_equal(g0[n0], g2[n0])
+
+
+def _circuit_plan(T, ctx, cfg, prec, cap, open_q, cycles=None, seed=0, restarts=4, rect=None):
+    if rect:
+        sites, cp = workloads.rect_grid(*rect)
+        c = workloads.random_circuit(sites, cp, cycles, seed)
+    else:
+        c = workloads.config_circuit(cfg, cycles=cycles)
+    from paper_2407_00769_amd import circuit_network as cn
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    ssa, sl, _ = T.tnc_search(net, len(r), open_q, cap, restarts=restarts, seed=seed)
+    return c, st, net, ssa, sl
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config0_matches_statevector(T, ctx, prec):
+    c, st, net, ssa, sl = _circuit_plan(T, ctx, 0, prec, 30, list(range(12)))
+    bits = workloads.uniform_bitstrings(12, 64, 1)
+    ref = statevector.amplitudes(c, bits)
+    plan = T.tnc_plan_create(ctx, net, ssa, sl, list(range(12)), prec)
+    out, rep = T.tnc_execute(plan, bits, 0, 1)
+    f = metrics.fidelity(ref, out)
+    rl = metrics.rel_l2(out, ref)
+    if prec == "c64":
+        assert f >= 1 - 1e-8 and rl <= 1e-4, (f, rl)
+    elif prec.startswith("f16"):
+        assert f >= 0.999 and rl <= 0.05, (f, rl)
+    else:
+        assert f >= 0.99, (f, rl)
+    T.tnc_plan_destroy(plan)
+    T.tnc_network_destroy(net)
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16_4m", "f16_3m"])
+def test_sliced_sum_matches_statevector(T, ctx, prec):
+    open_q = list(range(10, 16))
+    c, st, net, ssa, sl = _circuit_plan(T, ctx, None, prec, 10, open_q, cycles=10, seed=3, rect=(4, 4))
+    assert len(sl) >= 3
+    bits = workloads.prefix_bitstrings(16, open_q, 200, 9)
+    ref = statevector.amplitudes(c, bits)
+    plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, prec)
+    n = 1 << len(sl)
+    out, rep = T.tnc_execute(plan, bits, 0, n)
+    assert rep["slices"] == n
+    f = metrics.fidelity(ref, out)
+    assert f >= (1 - 1e-8 if prec == "c64" else 0.999), f
+    # a partial block equals the sum of projected state vectors of its slices
+    lo, hi = 1, min(n, 6)
+    part, _ = T.tnc_execute(plan, bits, lo, hi)
+    acc = np.zeros(len(bits), complex)
+    for sigma in range(lo, hi):
+        wf = {st.label_wire[l]: (sigma >> j) & 1 for j, l in enumerate(sl)}
+        acc += statevector.amplitudes(c, bits, wire_fix=wf)
+    assert metrics.fidelity(acc, part) >= (1 - 1e-8 if prec == "c64" else 0.999)
+    assert metrics.rel_l2(part, acc) <= (1e-4 if prec == "c64" else 0.05)
+    # disjoint ranges add up to the whole
+    a, _ = T.tnc_execute(plan, bits, 0, n // 2)
+    b, _ = T.tnc_execute(plan, bits, n // 2, n)
+    np.testing.assert_allclose(a + b, out, rtol=0, atol=1e-12 * np.max(np.abs(out)))
+    # determinism
+    again, _ = T.tnc_execute(plan, bits, 0, n)
+    np.testing.assert_array_equal(again, out)
+    T.tnc_plan_destroy(plan)
+    T.tnc_network_destroy(net)
+
+
+def test_graph_equals_stepwise(T, ctx, monkeypatch):
+    open_q = list(range(10, 16))
+    c, st, net, ssa, sl = _circuit_plan(T, ctx, None, "f16_4m", 10, open_q, cycles=8, seed=4, rect=(4, 4))
+    bits = workloads.prefix_bitstrings(16, open_q, 64, 2)
+    p1 = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
+    monkeypatch.setenv("TNC_NO_GRAPH", "1")
+    p2 = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
+    n = 1 << len(sl)
+    o1, r1 = T.tnc_execute(p1, bits, 0, n)
+    o2, r2 = T.tnc_execute(p2, bits, 0, n)
+    assert r1["graph_launches"] >= 1 and r2["graph_launches"] == 0
+    np.testing.assert_array_equal(o1, o2)
+    # one slice in flight gives the same bits as many (each slice's arithmetic is independent)
+    p3 = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m", max_slices_in_flight=1)
+    o3, _ = T.tnc_execute(p3, bits, 0, n)
+    np.testing.assert_array_equal(o1, o3)
+    for p in (p1, p2, p3):
+        T.tnc_plan_destroy(p)
+    T.tnc_network_destroy(net)
+
+
+def test_execute_rejects_bad_calls(T, ctx):
+    open_q = list(range(10, 16))
+    c, st, net, ssa, sl = _circuit_plan(T, ctx, None, "c64", 10, open_q, cycles=6, seed=5, rect=(4, 4))
+    plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "c64")
+    bits = workloads.prefix_bitstrings(16, open_q, 8, 2)
+    with pytest.raises(T.TncError):
+        T.tnc_execute(plan, bits, 0, (1 << len(sl)) + 1)
+    bad = bits.copy()
+    bad[0] ^= np.uint64(1)   # qubit 0 is closed: the request disagrees on it
+    with pytest.raises(T.TncError):
+        T.tnc_execute(plan, bad, 0, 1)
+    # empty range: zeros
+    z, _ = T.tnc_execute(plan, bits, 1, 1)
+    assert np.all(z == 0)
+    T.tnc_plan_destroy(plan)
+    # a workspace too small for one slice
+    tiny = torch.empty(4096, dtype=torch.uint8, device="cuda:0")
+    c2 = T.tnc_create(0, tiny, stream=torch.cuda.Stream())
+    with pytest.raises(T.TncError) as e:
+        T.tnc_plan_create(c2, net, ssa, sl, open_q, "c64")
+    assert e.value.code == -2
+    T.tnc_destroy(c2)
+    T.tnc_network_destroy(net)

@@ -1,0 +1,122 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point the header declares, validates networks and paths, and its
+planner derives the same per-step GEMM shapes a plain einsum implies."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+T = pytest.importorskip("paper_2407_00769_amd._tnc", reason="libtnc.so not built")
+from paper_2407_00769_amd import circuit_network as cn  # noqa: E402
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tnc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(T.lib, n), n
+    assert set(names) == set(T.EXPORTED)
+    assert "gfx950" in T.tnc_version()
+
+
+def _net(cfg=0, cycles=None):
+    c = workloads.config_circuit(cfg, cycles=cycles)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    return c, st, T.tnc_network_create(r, l, d, c.n_qubits, o), len(r)
+
+
+def test_network_validation_errors():
+    # a label in three tensors
+    with pytest.raises(T.TncError) as e:
+        T.tnc_network_create([1, 1, 1], [0, 0, 0], None, 0, [])
+    assert e.value.code == -1
+    # repeated label inside one tensor
+    with pytest.raises(T.TncError):
+        T.tnc_network_create([2], [3, 3], None, 0, [])
+    # dangling label that is not an output
+    with pytest.raises(T.TncError):
+        T.tnc_network_create([2, 1], [0, 1, 0], None, 0, [])
+    # fine: two tensors sharing a label, an output on each
+    h = T.tnc_network_create([2, 2], [0, 1, 0, 2], None, 2, [1, 2])
+    T.tnc_network_destroy(h)
+
+
+def test_search_returns_a_valid_tree_and_meets_the_cap():
+    c, st, net, n = _net(0)
+    ssa, sl, cost = T.tnc_search(net, n, list(range(12)), 30, restarts=3, seed=5)
+    assert len(ssa) == 2 * (n - 1)
+    seen = set()
+    for i in range(n - 1):
+        a, b = ssa[2 * i], ssa[2 * i + 1]
+        assert a not in seen and b not in seen and a < n + i and b < n + i
+        seen.update((a, b))
+    assert len(sl) == 0
+    # a tight cap forces slicing and is met
+    open6 = list(range(6))
+    ssa2, sl2, cost2 = T.tnc_search(net, n, open6, 7, restarts=3, seed=5)
+    info = T.tnc_plan_analyze(net, ssa2, sl2, open6, "c64")
+    assert info["max_rank"] <= 7 and len(sl2) > 0
+    assert info["out_rank"] == 6
+    # determinism
+    assert np.array_equal(ssa2, T.tnc_search(net, n, open6, 7, restarts=3, seed=5)[0])
+    # an impossible cap (below the open output) is an error
+    with pytest.raises(T.TncError):
+        T.tnc_search(net, n, list(range(12)), 10, restarts=1, seed=5)
+
+
+def test_plan_analyze_rejects_bad_inputs():
+    c, st, net, n = _net(0)
+    ssa, sl, _ = T.tnc_search(net, n, list(range(12)), 30, restarts=1, seed=0)
+    bad = ssa.copy()
+    bad[1] = bad[0]
+    with pytest.raises(T.TncError):
+        T.tnc_plan_analyze(net, bad, [], list(range(12)), "c64")
+    with pytest.raises(T.TncError):   # an output label cannot be sliced
+        T.tnc_plan_analyze(net, ssa, [st.output_labels[0]], list(range(12)), "c64")
+    with pytest.raises(T.TncError):   # 3M needs 16-bit storage
+        T.tnc_plan_analyze(net, ssa, [], list(range(12)), 5)
+
+
+def _einsum_flops(tensors, ssa, open_labels):
+    """Per-step 8 * 2^|union| from plain label sets (the algorithmic count)."""
+    ts = [set(t) for t in tensors]
+    need = {}
+    for t in ts:
+        for l in t:
+            need[l] = need.get(l, 0) + 1
+    for l in open_labels:
+        need[l] = need.get(l, 0) + 1
+    total = 0.0
+    for i in range(len(ssa) // 2):
+        a, b = ts[ssa[2 * i]], ts[ssa[2 * i + 1]]
+        uni = a | b
+        total += 8.0 * 2 ** len(uni)
+        out = set()
+        for l in uni:
+            after = need[l] - (l in a) - (l in b)
+            if after > 0:
+                out.add(l)
+            need[l] = after + (1 if after > 0 else 0)
+        ts.append(out)
+    return total
+
+
+def test_planner_flops_match_label_count():
+    c, st, net, n = _net(0)
+    open_q = list(range(12))
+    ssa, sl, _ = T.tnc_search(net, n, open_q, 30, restarts=2, seed=3)
+    info = T.tnc_plan_analyze(net, ssa, sl, open_q, "f16_4m")
+    want = _einsum_flops([t.labels for t in st.tensors], list(ssa), st.output_labels)
+    assert info["flops_per_slice"] + info["flops_invariant"] == pytest.approx(want, rel=1e-12)
