@@ -102,7 +102,7 @@ def timed_kernels(T, plan, bits, n, n_steps, dtype_key, reps=3):
             d["bytes"] += steps["bytes"][i] * sl_per_launch * launches[i]
             if p[i] > 0:
                 m, nn, kk, b = steps["log2_mnkb"][i]
-                pa, pb = steps["perm_ab"][i]
+                pa, pb = (int(v == 2) for v in steps["perm_ab"][i])
                 pbytes = 0.0
                 if pa:
                     pbytes += 2.0 * es * 2.0 ** (b + m + kk)

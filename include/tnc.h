@@ -87,6 +87,7 @@ typedef struct {
     double permute_bytes_per_slice;/* the part of bytes_per_slice spent in permutes        */
     double peak_bytes;             /* arena bytes needed at slices_in_flight               */
     double peak_elems_per_slice;   /* largest tensor of one slice, in complex entries      */
+    double tune_seconds;           /* host time spent timing kernel variants at plan time  */
 } tnc_plan_stats;
 
 /* Results of one tnc_execute. */
@@ -147,7 +148,10 @@ int tnc_search(const tnc_network *net, int32_t n_open, const int32_t *open_qubit
 
 /* ------------------------------------------------------------------ plan */
 
-/* Compile a path for execution on ctx's device.
+/* Compile a path for execution on ctx's device.  Every step's GEMM kernel
+ * variant is chosen by timing the candidates on the step's own operands
+ * (environment: TNC_TUNE=0 keeps the shape-based default; TNC_TUNE_CACHE names
+ * a file that persists the choices).
  * ssa_pairs[2*n_steps]: the path (a full binary tree over all tensors).
  * sliced_labels[n_sliced]: labels fixed per slice; slice s sets
  *   sliced_labels[j] to bit j of s.  Must not be output labels.
@@ -169,6 +173,14 @@ int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats);
 int tnc_plan_analyze(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
                      int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
                      const int32_t *open_qubits, tnc_precision prec, tnc_plan_stats *stats);
+
+/* Host-only per-step description of a path (arrays as in tnc_plan_steps,
+ * capacity n_steps, each may be NULL). */
+int tnc_plan_analyze_steps(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                           int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
+                           const int32_t *open_qubits, tnc_precision prec, int32_t *log2_mnkb,
+                           int32_t *kernel, int32_t *dep, int32_t *perm_ab, double *flops,
+                           double *bytes);
 
 /* Sum the amplitudes of slices [slice_begin, slice_end) for each bitstring.
  * bitstrings: host, n_bitstrings values; they must agree on every closed qubit
@@ -193,7 +205,8 @@ int tnc_plan_step_times(const tnc_plan *plan, int32_t n_steps, double *gemm_ms, 
 
 /* Per-step static description (host arrays of capacity n_steps, each may be
  * NULL): log2 of M, N, K and of the inner batch; the kernel variant id; 1 if
- * the step depends on the slice; 1/0 if its A / B operand is permuted;
+ * the step depends on the slice; the stride class of its A and B operands
+ * (0 read in place as [free][k], 1 read in place as [k][free], 2 permuted first);
  * algorithmic real flops per slice (8 B M N K) and GEMM bytes per slice
  * (A + B + C at the storage size). */
 int tnc_plan_steps(const tnc_plan *plan, int32_t n_steps, int32_t *log2_mnkb /* 4 per step */,

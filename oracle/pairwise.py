@@ -39,3 +39,9 @@ def entry(a_at, a_labels, b_at, b_labels, c_labels, c_values):
         v.update(zip(reduced, vals))
         acc += complex(a_at(v)) * complex(b_at(v))
     return acc
+
+
+def entry_dot(a_vals, b_vals):
+    """One output entry from the operand entries along the reduced labels
+    (already gathered in matching order): sum_k a_k b_k in FP64."""
+    return complex(np.dot(np.asarray(a_vals, np.complex128), np.asarray(b_vals, np.complex128)))

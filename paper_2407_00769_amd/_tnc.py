@@ -40,7 +40,8 @@ class tnc_plan_stats(ctypes.Structure):
                 ("max_rank", ctypes.c_int32), ("slices_in_flight", ctypes.c_int32), ("out_rank", ctypes.c_int32),
                 ("flops_per_slice", ctypes.c_double), ("flops_invariant", ctypes.c_double),
                 ("bytes_per_slice", ctypes.c_double), ("permute_bytes_per_slice", ctypes.c_double),
-                ("peak_bytes", ctypes.c_double), ("peak_elems_per_slice", ctypes.c_double)]
+                ("peak_bytes", ctypes.c_double), ("peak_elems_per_slice", ctypes.c_double),
+                ("tune_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +78,9 @@ _SIGS = {
     "tnc_plan_step_times": (ctypes.c_int, [vp, ctypes.c_int32, c_double_p, c_double_p, c_int32_p]),
     "tnc_plan_steps": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, c_int32_p, c_int32_p, c_int32_p, c_double_p,
                                       c_double_p]),
+    "tnc_plan_analyze_steps": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
+                                              ctypes.c_int32, c_int32_p, ctypes.c_int, c_int32_p, c_int32_p,
+                                              c_int32_p, c_int32_p, c_double_p, c_double_p]),
     "tnc_contract": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_int32, c_int32_p, vp, ctypes.c_int32, c_int32_p,
                                     vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_double_p, c_float_p]),
     "tnc_mlp_train": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, ctypes.c_int32, ctypes.c_int32,
@@ -240,19 +244,40 @@ def tnc_plan_step_times(plan, n_steps):
     return g, p, n
 
 
-def tnc_plan_steps(plan, n_steps) -> dict:
-    """Static per-step shapes, kernels and algorithmic work."""
-    mnkb = np.zeros(4 * n_steps, dtype=np.int32)
-    kern = np.zeros(n_steps, dtype=np.int32)
-    dep = np.zeros(n_steps, dtype=np.int32)
-    pab = np.zeros(2 * n_steps, dtype=np.int32)
-    fl = np.zeros(n_steps, dtype=np.float64)
-    by = np.zeros(n_steps, dtype=np.float64)
-    _check(lib.tnc_plan_steps(plan, n_steps, mnkb.ctypes.data_as(c_int32_p), kern.ctypes.data_as(c_int32_p),
-                              dep.ctypes.data_as(c_int32_p), pab.ctypes.data_as(c_int32_p),
-                              fl.ctypes.data_as(c_double_p), by.ctypes.data_as(c_double_p)))
+def _step_arrays(n_steps):
+    return (np.zeros(4 * n_steps, dtype=np.int32), np.zeros(n_steps, dtype=np.int32),
+            np.zeros(n_steps, dtype=np.int32), np.zeros(2 * n_steps, dtype=np.int32),
+            np.zeros(n_steps, dtype=np.float64), np.zeros(n_steps, dtype=np.float64))
+
+
+def _step_ptrs(arrs):
+    mnkb, kern, dep, pab, fl, by = arrs
+    return (mnkb.ctypes.data_as(c_int32_p), kern.ctypes.data_as(c_int32_p), dep.ctypes.data_as(c_int32_p),
+            pab.ctypes.data_as(c_int32_p), fl.ctypes.data_as(c_double_p), by.ctypes.data_as(c_double_p))
+
+
+def _step_dict(arrs):
+    mnkb, kern, dep, pab, fl, by = arrs
     return {"log2_mnkb": mnkb.reshape(-1, 4), "kernel": kern, "dep": dep, "perm_ab": pab.reshape(-1, 2),
             "flops": fl, "bytes": by}
+
+
+def tnc_plan_steps(plan, n_steps) -> dict:
+    """Static per-step shapes, kernels and algorithmic work."""
+    arrs = _step_arrays(n_steps)
+    _check(lib.tnc_plan_steps(plan, n_steps, *_step_ptrs(arrs)))
+    return _step_dict(arrs)
+
+
+def tnc_plan_analyze_steps(net, ssa, sliced, open_qubits, precision) -> dict:
+    s, sp = _i32(ssa)
+    sl, slp = _i32(sliced)
+    oq, op = _i32(open_qubits)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n_steps = len(s) // 2
+    arrs = _step_arrays(n_steps)
+    _check(lib.tnc_plan_analyze_steps(net, n_steps, sp, len(sl), slp, len(oq), op, prec, *_step_ptrs(arrs)))
+    return _step_dict(arrs)
 
 
 def tnc_contract(ctx, precision, A, a_labels, B, b_labels, C, c_labels, scale_log2=0):

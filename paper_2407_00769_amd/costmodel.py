@@ -1,0 +1,97 @@
+"""Step-time data for the learned cost model (host-side orchestration).
+
+Rows come from the engine's own measurements: plans of random circuits are
+executed with step timing on (HIP events around each step's permutes and
+GEMM), and every launch becomes one row
+
+    features = (log2 M, log2 N, log2 K, log2 batch, stride class A,
+                stride class B, dtype, algorithm)
+    target   = log2(device microseconds of the launch, permutes included)
+
+where batch counts the inner batch times the slices the launch carries,
+stride class is 0 (operand read in place as [free][k]), 1 (in place as
+[k][free]) or 2 (permuted first), dtype is 0 complex64, 1 FP16, 2 BF16 and
+algorithm is 0 for 4M, 1 for 3M.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import _tnc as T
+from . import circuit_network as cn
+
+DTYPE_CODE = {"c64": 0, "f16_4m": 1, "f16_3m": 1, "bf16_4m": 2, "bf16_3m": 2}
+ALGO_CODE = {"c64": 0, "f16_4m": 0, "f16_3m": 1, "bf16_4m": 0, "bf16_3m": 1}
+
+
+def step_rows(plan, n_slices, prec, reps=1):
+    """(X, y, flops) rows of one timed execute per rep (bitstrings: all zeros on
+    closed qubits)."""
+    info = T.tnc_plan_info(plan)
+    n_steps = info["n_steps"]
+    steps = T.tnc_plan_steps(plan, n_steps)
+    T.tnc_plan_set_timing(plan, True)
+    X, y, fl = [], [], []
+    bits = np.zeros(1, dtype=np.uint64)
+    for _ in range(reps):
+        T.tnc_execute(plan, bits, 0, n_slices)
+        g, p, launches = T.tnc_plan_step_times(plan, n_steps)
+        for i in range(n_steps):
+            if launches[i] == 0:
+                continue
+            per_launch_slices = n_slices / launches[i] if steps["dep"][i] else 1.0
+            m, n, k, b = steps["log2_mnkb"][i]
+            sa, sb = steps["perm_ab"][i]
+            us = (g[i] + p[i]) * 1e3 / launches[i]
+            if us <= 0:
+                continue
+            X.append([m, n, k, b + math.log2(per_launch_slices), sa, sb, DTYPE_CODE[prec], ALGO_CODE[prec]])
+            y.append(math.log2(us))
+            fl.append(steps["flops"][i] * per_launch_slices)
+    T.tnc_plan_set_timing(plan, False)
+    return X, y, fl
+
+
+def collect(ctx, circuits, precisions, caps, open_counts, restarts=4, seed=0, reps=1, max_slices=64):
+    """Timing rows from every (circuit, precision, cap, open count) plan.
+
+    circuits: iterable of workloads.Circuit.  Returns (X float32 [n, 8],
+    y float32 [n], flops float64 [n])."""
+    import workloads
+
+    X, y, fl = [], [], []
+    for c in circuits:
+        st = workloads.tn_structure(c)
+        r, l, d, o = cn.network_arrays(c, st)
+        net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+        for cap in caps:
+            for n_open in open_counts:
+                open_q = list(range(c.n_qubits - n_open, c.n_qubits))
+                try:
+                    ssa, sl, _ = T.tnc_search(net, len(r), open_q, cap, restarts=restarts, seed=seed)
+                except T.TncError:
+                    continue
+                n_sl = min(1 << len(sl), max_slices)
+                for prec in precisions:
+                    try:
+                        plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, prec)
+                    except T.TncError:
+                        continue
+                    a, b, f = step_rows(plan, n_sl, prec, reps)
+                    X += a
+                    y += b
+                    fl += f
+                    T.tnc_plan_destroy(plan)
+        T.tnc_network_destroy(net)
+    return np.array(X, np.float32), np.array(y, np.float32), np.array(fl, np.float64)
+
+
+def flop_model_fit(flops, y):
+    """The FLOP cost model with its one scale fitted: log2 t = log2 flops + c."""
+    return float(np.median(np.asarray(y, np.float64) - np.log2(np.maximum(flops, 1.0))))
+
+
+def flop_model_predict(flops, c):
+    return np.log2(np.maximum(flops, 1.0)) + c

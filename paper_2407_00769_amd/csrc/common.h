@@ -69,10 +69,13 @@ struct PermuteDesc {
 };
 
 // Everything one step needs at run time.  Sizes are complex entries.
+// Operand orientation: A is [m][k] (a_kc = 1) or [k][m]; B is [n][k]
+// (b_kc = 1) or [k][n]; C is written [m][n] (c_nc = 1) or [n][m].
 struct GemmShape {
     int64_t M, N, K, nb;        // rows, cols, reduced, inner batch
     int64_t sA, sB, sC;         // slice strides (0 = shared by every slice)
     int64_t bA, bB, bC;         // inner-batch strides
+    int a_kc = 1, b_kc = 1, c_nc = 1, pad_ = 0;
 };
 
 // Scale bookkeeping of the 16-bit forms, per tensor and slice.
@@ -88,15 +91,20 @@ struct ScaleRefs {
     uint32_t *flag;                 // set nonzero on range overflow
 };
 
+// Target exponent of the largest stored 16-bit component (see device_util.h).
+constexpr int kTargetLog2Host = 13;
+
 // Kernel variant ids (autotuned per step).
 enum KernelId : int {
     K_NAIVE = 0,      // thread per output entry; any shape
     K_SKINNY_N = 1,   // row per thread, N <= 16, VALU
-    K_MFMA_S = 2,     // matrix-core tile 64 x 32c
-    K_MFMA_M = 3,     // matrix-core tile 128 x 32c
-    K_MFMA_L = 4,     // matrix-core tile 128 x 64c
-    K_MFMA_W = 5,     // matrix-core tile 256 x 16c (thin N)
-    K_COUNT = 6
+    K_MFMA_S = 2,     // matrix-core tiles (rows x complex cols; see tile_of)
+    K_MFMA_M = 3,
+    K_MFMA_L = 4,
+    K_MFMA_W = 5,     // tall thin tile
+    K_MFMA_XL = 6,    // large tiles for compute-bound steps
+    K_MFMA_L2 = 7,
+    K_COUNT = 8
 };
 const char *kernel_name(int k);
 

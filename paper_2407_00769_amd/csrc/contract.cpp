@@ -99,9 +99,41 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
             no = keep_order(lq, fq);
         }
         std::vector<int> ko = keep_order(lr, k);
-        std::vector<int> want_r = cat({&bo, &mo, &ko}), want_q = cat({&bo, &no, &ko});
+        // operands keep their layout when it reads as [batch][free][k] or [batch][k][free]
+        auto fits = [&](const std::vector<int> &l, const std::vector<int> &fo, int &kc) {
+            if (l == cat({&bo, &fo, &ko})) { kc = 1; return true; }
+            if (l == cat({&bo, &ko, &fo})) { kc = 0; return true; }
+            return false;
+        };
+        int r_kc = 1, q_kc = 1;
+        if (!direct) {
+            // free orders are ours to choose: take them from the operands
+            mo = keep_order(lr, fr);
+            no = keep_order(lq, fq);
+        }
+        bool keep_r = fits(lr, mo, r_kc);
+        if (!keep_r) r_kc = 1;
+        if (!fits(lq, no, q_kc)) {
+            // try B's own k order (then R may need the permute instead)
+            std::vector<int> ko2 = keep_order(lq, k);
+            std::vector<int> save = ko;
+            ko = ko2;
+            int t1 = 1, t2 = 1;
+            if (fits(lq, no, t2) && !keep_r) {
+                q_kc = t2;
+            } else {
+                ko = save;
+                q_kc = 1;
+            }
+            (void)t1;
+        }
+        std::vector<int> want_r = r_kc ? cat({&bo, &mo, &ko}) : cat({&bo, &ko, &mo});
+        std::vector<int> want_q = q_kc ? cat({&bo, &no, &ko}) : cat({&bo, &ko, &no});
         std::vector<int> gemm_c = cat({&bo, &mo, &no});
-        const bool perm_r = want_r != lr, perm_q = want_q != lq, perm_c = gemm_c != lc;
+        std::vector<int> gemm_ct = cat({&bo, &no, &mo});
+        int c_nc = 1;
+        if (gemm_c != lc && gemm_ct == lc) c_nc = 0;
+        const bool perm_r = want_r != lr, perm_q = want_q != lq, perm_c = (c_nc ? gemm_c : gemm_ct) != lc;
         const int es = elem_bytes(dt);
         const int64_t nr = (int64_t)1 << lr.size(), nq = (int64_t)1 << lq.size(), nc = (int64_t)1 << lc.size();
         auto al256 = [](int64_t v) { return (v + 255) & ~(int64_t)255; };
@@ -134,6 +166,9 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
         g.bA = g.M * g.K;
         g.bB = g.N * g.K;
         g.bC = g.M * g.N;
+        g.a_kc = r_kc;
+        g.b_kc = q_kc;
+        g.c_nc = c_nc;
         void *pc = perm_c ? (void *)(ctx->ws + off_c) : C;
         // scale bookkeeping in the context's small buffer: maxA = maxB = 1.0,
         // so shift = growth - target = scale_log2
@@ -168,7 +203,7 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
         }
         launch_gemm(kid, dt, al, pr, pq, pc, g, 1, dt != Dtype::C64 ? &sc : nullptr, st);
         HIP_CHECK(hipEventRecord(ev[3], st));
-        if (perm_c) launch_permute(dt, pc, C, make_permute(gemm_c, lc), nc, 1, 0, nullptr, 0, st);
+        if (perm_c) launch_permute(dt, pc, C, make_permute(c_nc ? gemm_c : gemm_ct, lc), nc, 1, 0, nullptr, 0, st);
         HIP_CHECK(hipEventRecord(ev[4], st));
         HIP_CHECK(hipEventSynchronize(ev[4]));
         if (times_ms) {

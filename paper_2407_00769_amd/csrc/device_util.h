@@ -91,7 +91,7 @@ __device__ __forceinline__ float absmax_nan(float a, float b) {
 // All 16-bit results are stored as value * 2^-shift with
 //   shift = floor(log2 maxA) + floor(log2 maxB) + growth - kTargetLog2
 // so that the largest stored component lands near 2^kTargetLog2.
-constexpr int kTargetLog2 = 13;
+constexpr int kTargetLog2 = kTargetLog2Host;
 
 __device__ __forceinline__ int floor_log2_pos(float x) {
     int e;

@@ -4,7 +4,9 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -280,6 +282,126 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
     p->use_graph = !(ng && ng[0] == '1') && ctx->stream != nullptr;
 }
 
+// ------------------------------------------------------------------ autotuner
+// Each step's GEMM is timed with every kernel variant that supports its shape
+// and operand orientation, on the step's real arena operands, and the fastest
+// is kept.  Results are cached per (dtype, algorithm, log2 M, N, K, batch,
+// orientation) for the process, and in the file named by TNC_TUNE_CACHE.
+namespace {
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_loaded = false;
+
+int ilog2(int64_t v) {
+    int r = 0;
+    while ((int64_t)1 << (r + 1) <= v) r++;
+    return r;
+}
+
+void tune_cache_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = getenv("TNC_TUNE_CACHE");
+    if (!f) return;
+    FILE *fp = fopen(f, "r");
+    if (!fp) return;
+    int a[10];
+    while (fscanf(fp, "%d %d %d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &a[6], &a[7], &a[8],
+                  &a[9]) == 10)
+        g_tune[TuneKey(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8])] = a[9];
+    fclose(fp);
+}
+
+void tune_cache_append(const TuneKey &k, int kid) {
+    const char *f = getenv("TNC_TUNE_CACHE");
+    if (!f) return;
+    FILE *fp = fopen(f, "a");
+    if (!fp) return;
+    fprintf(fp, "%d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+            std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), kid);
+    fclose(fp);
+}
+
+double autotune_plan(tnc_plan *p) {
+    const char *env = getenv("TNC_TUNE");
+    if (env && env[0] == '0') return 0.0;
+    Analysis &an = p->an;
+    const Dtype dt = an.dt;
+    hipStream_t st = p->ctx->stream;
+    uint8_t *ws = p->ctx->ws;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_cache_load();
+    // scale bookkeeping for tuning launches lives in the context's small buffer
+    struct Small {
+        uint32_t maxA, maxB, maxC, flag;
+        int growth, shift, pad0, pad1;
+        double expA, expB, expC;
+    } h{0x3f800000u, 0x3f800000u, 0u, 0u, kTargetLog2Host, 0, 0, 0, 0.0, 0.0, 0.0};
+    HIP_CHECK(hipMemcpyAsync(p->ctx->small, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    Small *d = (Small *)p->ctx->small;
+    ScaleRefs sc{};
+    sc.maxA = &d->maxA;
+    sc.maxB = &d->maxB;
+    sc.maxC = &d->maxC;
+    sc.flag = &d->flag;
+    sc.growth = &d->growth;
+    sc.shift = &d->shift;
+    sc.expA = &d->expA;
+    sc.expB = &d->expB;
+    sc.expC = &d->expC;
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    auto t_start = std::chrono::steady_clock::now();
+    for (auto &rec : an.steps) {
+        const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
+        const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank(), nz = (int64_t)1 << Z.rank();
+        GemmShape g{rec.M, rec.N, rec.K, rec.nb, A.dep ? na : 0, B.dep ? nbb : 0, nz, rec.M * rec.K, rec.N * rec.K,
+                    rec.M * rec.N};
+        g.a_kc = rec.a_kc;
+        g.b_kc = rec.b_kc;
+        g.c_nc = rec.c_nc;
+        const int Sl = rec.dep ? p->S : 1;
+        std::vector<int> cands;
+        for (int k = 1; k < K_COUNT; k++)
+            if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
+        if (cands.size() <= 1) continue;
+        TuneKey key((int)dt, (int)an.al, ilog2(g.M), ilog2(g.N), ilog2(g.K), ilog2(g.nb), g.a_kc, g.b_kc, g.c_nc);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            if (gemm_supported(it->second, dt, an.al, g)) rec.kernel = it->second;
+            continue;
+        }
+        const void *pa = ws + (rec.perm_a ? rec.scr_a : A.off);
+        const void *pb = ws + (rec.perm_b ? rec.scr_b : B.off);
+        void *pc = ws + Z.off;
+        double best = 1e30;
+        int best_k = rec.kernel;
+        for (int k : cands) {
+            launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);   // warm
+            HIP_CHECK(hipEventRecord(e0, st));
+            for (int r = 0; r < 2; r++) launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+            HIP_CHECK(hipEventRecord(e1, st));
+            HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_k = k;
+            }
+        }
+        rec.kernel = best_k;
+        g_tune[key] = best_k;
+        tune_cache_append(key, best_k);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+}
+}  // namespace
+
 extern "C" int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
                                int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
                                const int32_t *open_qubits, tnc_precision prec, int32_t max_slices_in_flight,
@@ -296,6 +418,7 @@ extern "C" int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_s
     try {
         p->an = analyze(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits, prec);
         build_plan(p, net->net, max_slices_in_flight);
+        p->tune_seconds = autotune_plan(p);
     } catch (...) {
         free_plan_device(p);
         delete p;
@@ -320,6 +443,7 @@ extern "C" int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats) {
     fill_stats(plan->an, *stats);
     stats->slices_in_flight = plan->S;
     stats->peak_bytes = (double)plan->peak;
+    stats->tune_seconds = plan->tune_seconds;
     API_END
 }
 
@@ -364,19 +488,26 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
     const void *pb = ws + B.off;
     if (tm) HIP_CHECK(hipEventRecord(tm->e[0], st));
     if (rec.perm_a) {
-        PermuteDesc d = make_permute(rec.a_from, A.labels);
-        int Sa = A.dep ? S_g : 1;
-        launch_permute(dt, ws + A.off, ws + rec.scr_a, d, na, Sa, A.dep ? na : 0, nullptr, A.dep ? na : 0, st);
+        if (!rec.hoist_a) {
+            PermuteDesc d = make_permute(rec.a_from, A.labels);
+            int Sa = A.dep ? S_g : 1;
+            launch_permute(dt, ws + A.off, ws + rec.scr_a, d, na, Sa, A.dep ? na : 0, nullptr, A.dep ? na : 0, st);
+        }
         pa = ws + rec.scr_a;
     }
     if (rec.perm_b) {
-        PermuteDesc d = make_permute(rec.b_from, B.labels);
-        int Sb = B.dep ? S_g : 1;
-        launch_permute(dt, ws + B.off, ws + rec.scr_b, d, nbb, Sb, B.dep ? nbb : 0, nullptr, B.dep ? nbb : 0, st);
+        if (!rec.hoist_b) {
+            PermuteDesc d = make_permute(rec.b_from, B.labels);
+            int Sb = B.dep ? S_g : 1;
+            launch_permute(dt, ws + B.off, ws + rec.scr_b, d, nbb, Sb, B.dep ? nbb : 0, nullptr, B.dep ? nbb : 0, st);
+        }
         pb = ws + rec.scr_b;
     }
     GemmShape g{rec.M, rec.N, rec.K, rec.nb, A.dep ? na : 0, B.dep ? nbb : 0, nz, rec.M * rec.K, rec.N * rec.K,
                 rec.M * rec.N};
+    g.a_kc = rec.a_kc;
+    g.b_kc = rec.b_kc;
+    g.c_nc = rec.c_nc;
     (void)es;
     ScaleRefs sc{};
     if (dt != Dtype::C64) {
@@ -427,6 +558,21 @@ void enqueue_block(tnc_plan *p, int64_t nsl, int64_t nbits, hipStream_t st, bool
     };
     for (int s = 0; s < (int)an.steps.size(); s++)
         if (!an.steps[s].dep) run(s, 1);
+    // permuted copies of invariant operands of dependent steps, once per call
+    for (int s = 0; s < (int)an.steps.size(); s++) {
+        const StepRec &rec = an.steps[s];
+        uint8_t *ws = p->ctx->ws;
+        if (rec.hoist_a) {
+            const TensorRec &A = an.tensors[rec.a];
+            launch_permute(dt, ws + A.off, ws + rec.scr_a, make_permute(rec.a_from, A.labels), (int64_t)1 << A.rank(),
+                           1, 0, nullptr, 0, st);
+        }
+        if (rec.hoist_b) {
+            const TensorRec &B = an.tensors[rec.b];
+            launch_permute(dt, ws + B.off, ws + rec.scr_b, make_permute(rec.b_from, B.labels), (int64_t)1 << B.rank(),
+                           1, 0, nullptr, 0, st);
+        }
+    }
     const TensorRec &R = an.tensors[an.root];
     for (int64_t g0 = 0; g0 < nsl; g0 += S) {
         const int S_g = (int)std::min<int64_t>(S, nsl - g0);
@@ -469,12 +615,10 @@ extern "C" int tnc_plan_step_times(const tnc_plan *plan, int32_t n_steps, double
     API_END
 }
 
-extern "C" int tnc_plan_steps(const tnc_plan *plan, int32_t n_steps, int32_t *log2_mnkb, int32_t *kernel, int32_t *dep,
-                              int32_t *perm_ab, double *flops, double *bytes) {
-    API_BEGIN
-    REQUIRE(plan, "plan is NULL");
-    const auto &st = plan->an.steps;
-    REQUIRE(n_steps >= (int)st.size(), "arrays too small");
+static void describe_steps(const Analysis &an, int32_t n_steps, int32_t *log2_mnkb, int32_t *kernel, int32_t *dep,
+                           int32_t *perm_ab, double *flops, double *bytes) {
+    const auto &st = an.steps;
+    if (n_steps < (int)st.size()) TNC_THROW(TNC_EINVAL, "arrays too small");
     for (size_t i = 0; i < st.size(); i++) {
         const StepRec &r = st[i];
         if (log2_mnkb) {
@@ -485,13 +629,31 @@ extern "C" int tnc_plan_steps(const tnc_plan *plan, int32_t n_steps, int32_t *lo
         }
         if (kernel) kernel[i] = r.kernel;
         if (dep) dep[i] = r.dep ? 1 : 0;
-        if (perm_ab) {
-            perm_ab[2 * i] = r.perm_a ? 1 : 0;
-            perm_ab[2 * i + 1] = r.perm_b ? 1 : 0;
+        if (perm_ab) {   // operand stride class: 0 in place [m][k], 1 in place [k][m], 2 permuted
+            perm_ab[2 * i] = r.perm_a ? 2 : (r.a_kc ? 0 : 1);
+            perm_ab[2 * i + 1] = r.perm_b ? 2 : (r.b_kc ? 0 : 1);
         }
         if (flops) flops[i] = r.flops;
         if (bytes) bytes[i] = r.bytes;
     }
+}
+
+extern "C" int tnc_plan_steps(const tnc_plan *plan, int32_t n_steps, int32_t *log2_mnkb, int32_t *kernel, int32_t *dep,
+                              int32_t *perm_ab, double *flops, double *bytes) {
+    API_BEGIN
+    REQUIRE(plan, "plan is NULL");
+    describe_steps(plan->an, n_steps, log2_mnkb, kernel, dep, perm_ab, flops, bytes);
+    API_END
+}
+
+extern "C" int tnc_plan_analyze_steps(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                                      int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
+                                      const int32_t *open_qubits, tnc_precision prec, int32_t *log2_mnkb,
+                                      int32_t *kernel, int32_t *dep, int32_t *perm_ab, double *flops, double *bytes) {
+    API_BEGIN
+    REQUIRE(net, "net is NULL");
+    Analysis an = analyze(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits, prec);
+    describe_steps(an, n_steps, log2_mnkb, kernel, dep, perm_ab, flops, bytes);
     API_END
 }
 

@@ -57,6 +57,7 @@ struct tnc_plan {
     // graph cache: (slices, bitstrings, bits pointer) -> executable graph
     std::map<std::tuple<int64_t, int64_t, const void *>, hipGraphExec_t> graphs;
     bool use_graph = true;
+    double tune_seconds = 0;
     bool timing = false;
     std::vector<double> step_ms, perm_ms;
     std::vector<int> step_launches;

@@ -1,8 +1,9 @@
 // Batched complex GEMM for one contraction step (paper Eq. contraction in
 // its pure-GEMM form, Sec. 3.3):
 //     C[s][b][m][n] = sum_k A[s][b][m][k] * B[s][b][n][k]
-// A is the large operand, B the small one; both are K-contiguous, C is
-// N-contiguous.  s is the slice in flight, b the inner batch.
+// s is the slice in flight, b the inner batch.  Each operand is stored in
+// either orientation (A as [m][k] or [k][m], B as [n][k] or [k][n]) and C is
+// written as [m][n] or [n][m], so the planner can skip most permutes.
 //
 // Forms:
 //   4M   -- one real GEMM  C'[m][2n+d] = sum_{k'} A'[m][k'] B'[k'][2n+d], with
@@ -10,7 +11,8 @@
 //           small operand padded on the fly to [B(re,-im), B(im,re)] (paper
 //           Eq. eq_modified2); 8 real flops per complex multiply-add.
 //   3M   -- T1 = Ar Br, T2 = Ai Bi, T3 = (Ar+Ai)(Br+Bi) with the sums rounded
-//           once to the storage type; Cr = T1 - T2, Ci = T3 - T1 - T2.
+//           once to the storage type; Cr = T1 - T2, Ci = T3 - T1 - T2
+//           (6 executed real flops per complex multiply-add).
 // 16-bit results are stored as value * 2^-shift (see device_util.h).
 #include <hip/hip_runtime.h>
 
@@ -25,6 +27,7 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 template <typename W> __device__ __forceinline__ float round_to_storage(float x);
 template <> __device__ __forceinline__ float round_to_storage<HalfWord>(float x) {
@@ -65,6 +68,16 @@ __device__ __forceinline__ float pow2_neg(int shift) {
     return __uint_as_float((uint32_t)(127 - shift) << 23);
 }
 
+__device__ __forceinline__ int64_t a_index(const GemmShape &g, int64_t m, int64_t k) {
+    return g.a_kc ? m * g.K + k : k * g.M + m;
+}
+__device__ __forceinline__ int64_t b_index(const GemmShape &g, int64_t n, int64_t k) {
+    return g.b_kc ? n * g.K + k : k * g.N + n;
+}
+__device__ __forceinline__ int64_t c_index(const GemmShape &g, int64_t m, int64_t n) {
+    return g.c_nc ? m * g.N + n : n * g.M + m;
+}
+
 // ===================================================================== naive: thread per output
 
 template <typename W, bool SCALE, bool M3>
@@ -82,13 +95,19 @@ __global__ void __launch_bounds__(256) gemm_naive_kernel(const W *__restrict__ A
     const int64_t total = g.M * g.N;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t m = i / g.N, n = i - m * g.N;
-        const W *ar = Ap + m * g.K;
-        const W *br = Bp + n * g.K;
+        // consecutive threads walk the contiguous dimension of C
+        int64_t m, n;
+        if (g.c_nc) {
+            m = i / g.N;
+            n = i - m * g.N;
+        } else {
+            n = i / g.M;
+            m = i - n * g.M;
+        }
         float re = 0.f, im = 0.f;
         if (!M3) {
             for (int64_t k = 0; k < g.K; k++) {
-                float2 a = unpack(ar[k]), bb = unpack(br[k]);
+                float2 a = unpack(Ap[a_index(g, m, k)]), bb = unpack(Bp[b_index(g, n, k)]);
                 re = fmaf(a.x, bb.x, re);
                 re = fmaf(-a.y, bb.y, re);
                 im = fmaf(a.x, bb.y, im);
@@ -97,7 +116,7 @@ __global__ void __launch_bounds__(256) gemm_naive_kernel(const W *__restrict__ A
         } else {
             float t1 = 0.f, t2 = 0.f, t3 = 0.f;
             for (int64_t k = 0; k < g.K; k++) {
-                float2 a = unpack(ar[k]), bb = unpack(br[k]);
+                float2 a = unpack(Ap[a_index(g, m, k)]), bb = unpack(Bp[b_index(g, n, k)]);
                 t1 = fmaf(a.x, bb.x, t1);
                 t2 = fmaf(a.y, bb.y, t2);
                 t3 = fmaf(round_to_storage<W>(a.x + a.y), round_to_storage<W>(bb.x + bb.y), t3);
@@ -105,7 +124,7 @@ __global__ void __launch_bounds__(256) gemm_naive_kernel(const W *__restrict__ A
             re = t1 - t2;
             im = t3 - t1 - t2;
         }
-        mx = fmaxf(mx, store_entry<W, SCALE>(Cp + i, re, im, scale));
+        mx = fmaxf(mx, store_entry<W, SCALE>(Cp + c_index(g, m, n), re, im, scale));
     }
     finish_max<SCALE>(sc, s, mx);
 }
@@ -143,17 +162,23 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(const W *__restrict__ 
         const int kc = (int)((g.K - k0) < KC ? (g.K - k0) : KC);
         __syncthreads();
         for (int e = threadIdx.x; e < NN * KC; e += blockDim.x) {
-            int j = e / KC, kk = e - j * KC;
+            int j, kk;
+            if (g.b_kc) {
+                j = e / KC;
+                kk = e - j * KC;
+            } else {
+                kk = e / NN;
+                j = e - kk * NN;
+            }
             float2 v = make_float2(0.f, 0.f);
-            if (j < nn && kk < kc) v = unpack(Bp[(n0 + j) * g.K + k0 + kk]);
+            if (j < nn && kk < kc) v = unpack(Bp[b_index(g, n0 + j, k0 + kk)]);
             Bs[j][kk] = v;
             if constexpr (M3) Bsum[j][kk] = round_to_storage<W>(v.x + v.y);
         }
         __syncthreads();
         if (live) {
-            const W *ar = Ap + m * g.K + k0;
             for (int kk = 0; kk < kc; kk++) {
-                float2 a = unpack(ar[kk]);
+                float2 a = unpack(Ap[a_index(g, m, k0 + kk)]);
                 if constexpr (!M3) {
 #pragma unroll
                     for (int j = 0; j < NN; j++) {
@@ -178,7 +203,6 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(const W *__restrict__ 
     }
     float mx = 0.f;
     if (live) {
-        W *cr = Cp + m * g.N + n0;
 #pragma unroll
         for (int j = 0; j < NN; j++) {
             if (j < nn) {
@@ -190,20 +214,23 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(const W *__restrict__ 
                     re = acc[j].x - acc[j].y;
                     im = t3[j] - acc[j].x - acc[j].y;
                 }
-                mx = fmaxf(mx, store_entry<W, SCALE>(cr + j, re, im, scale));
+                mx = fmaxf(mx, store_entry<W, SCALE>(Cp + c_index(g, m, n0 + j), re, im, scale));
             }
         }
     }
     finish_max<SCALE>(sc, s, mx);
 }
 
-// ===================================================================== matrix cores, 16-bit 4M
+// ===================================================================== matrix cores, 16-bit
 //
-// Block tile BM rows x BN complex columns, k-tile BK complex; WM x WN waves,
-// each wave (BM/WM) x (2BN/WN) real outputs as 32x32 MFMA blocks.
-// v_mfma_f32_32x32x16_{f16,bf16}: lane l holds A'[l%32][8(l/32)+0..7] and
-// B'[8(l/32)+0..7][l%32]; result register r of lane l is row
+// Block tile BM rows x BN complex columns, k-tile BK complex; WM x WN waves.
+// v_mfma_f32_32x32x16_{f16,bf16}: lane l holds A[l%32][8(l/32)+0..7] and
+// B[8(l/32)+0..7][l%32]; result register r of lane l is row
 // 8(r/4) + 4(l/32) + r%4, column l%32.
+//   4M: the real GEMM of the header (k' = 2k + c, columns 2n + d); a wave
+//       owns (BM/WM) rows x (2BN/WN) real columns.
+//   3M: three real GEMMs over k; a wave owns (BM/WM) rows x (BN/WN) complex
+//       columns with three accumulators per 32x32 block.
 
 template <bool BF> __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
     if constexpr (BF)
@@ -216,30 +243,56 @@ template <bool BF> __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, 
 
 __device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
 
+// rounded re + im of a 16-bit complex word, as 16-bit bits
+template <bool BF> __device__ __forceinline__ uint32_t sum_bits(uint32_t w) {
+    if constexpr (BF) {
+        float re = __uint_as_float(w << 16), im = __uint_as_float(w & 0xffff0000u);
+        return f2bf_bits(re + im);
+    } else {
+        float re = __half2float(__ushort_as_half((unsigned short)(w & 0xffffu)));
+        float im = __half2float(__ushort_as_half((unsigned short)(w >> 16)));
+        return f2h_bits(re + im);
+    }
+}
+
 // XCD-aware order: consecutive tiles of one row block land on one XCD (8 per chip).
 __device__ __forceinline__ int64_t xcd_tile(int64_t w, int64_t total) {
     if (total % 8) return w;
     return (w % 8) * (total / 8) + w / 8;
 }
 
-template <bool BF, int BM, int BN, int BK, int WM, int WN, bool SCALE>
-__global__ void __launch_bounds__(64 * WM * WN)
-    gemm_mfma_h4m_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t *__restrict__ C,
-                         GemmShape g, ScaleRefs sc) {
-    using W = typename std::conditional<BF, Bf16Word, HalfWord>::type;
-    constexpr int NT = 64 * WM * WN;
-    constexpr int PAD = 4;
-    constexpr int LDA = BK + PAD, LDB = BK + PAD;
-    constexpr int WTM = BM / WM, WTN = 2 * BN / WN;   // wave tile: rows, real cols
-    constexpr int FM = WTM / 32, FN = WTN / 32;
+template <bool BF, bool M3, int BM, int BN, int BK, int WM, int WN>
+struct HTile {
+    static constexpr int NT = 64 * WM * WN;
+    // 4M: LDS holds complex words; 3M: three planes of 16-bit values
+    static constexpr int PAD = M3 ? 8 : 4;                    // in elements of the LDS row type
+    static constexpr int LDA = BK + PAD, LDB = BK + PAD;
+    static constexpr int A_ELEMS = M3 ? 3 * BM * LDA : BM * LDA;   // halves (3M) or words (4M)
+    static constexpr int B_ELEMS = M3 ? 3 * BN * LDB : BN * LDB;
+    static constexpr int ESZ = M3 ? 2 : 4;
+    static constexpr int AB_BYTES = 2 * (A_ELEMS + B_ELEMS) * ESZ;
+    static constexpr int C_BYTES = BM * BN * 4;
+    static constexpr int LDS_BYTES = AB_BYTES > C_BYTES ? AB_BYTES : C_BYTES;
+    static constexpr int WTM = BM / WM;
+    static constexpr int WTN = M3 ? BN / WN : 2 * BN / WN;    // complex (3M) or real (4M) columns
+    static constexpr int FM = WTM / 32, FN = WTN / 32;
+    static constexpr int KSTEP = M3 ? 16 : 8;                  // complex k per MFMA
+    static constexpr int A_CHUNKS = BM * BK / 4, B_CHUNKS = BN * BK / 4;
+    static constexpr int A_PER = (A_CHUNKS + NT - 1) / NT, B_PER = (B_CHUNKS + NT - 1) / NT;
     static_assert(FM >= 1 && FN >= 1, "wave tile too small");
-    constexpr int A_CHUNKS = BM * BK / 4, B_CHUNKS = BN * BK / 4;   // 16-byte chunks
-    constexpr int A_PER = (A_CHUNKS + NT - 1) / NT, B_PER = (B_CHUNKS + NT - 1) / NT;
-    constexpr int LDS_AB = 2 * (BM * LDA + BN * LDB);
-    constexpr int LDS_C = BM * BN;
-    __shared__ uint32_t lds[LDS_AB > LDS_C ? LDS_AB : LDS_C];
-    auto As = [&](int buf) { return lds + buf * (BM * LDA); };
-    auto Bs = [&](int buf) { return lds + 2 * BM * LDA + buf * (BN * LDB); };
+    static_assert(BK % KSTEP == 0, "k tile");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+template <bool BF, bool M3, int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+    gemm_mfma_h_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t *__restrict__ C,
+                       GemmShape g, ScaleRefs sc) {
+    using Tl = HTile<BF, M3, BM, BN, BK, WM, WN>;
+    using W = typename std::conditional<BF, Bf16Word, HalfWord>::type;
+    constexpr int NT = Tl::NT, LDA = Tl::LDA, LDB = Tl::LDB, FM = Tl::FM, FN = Tl::FN;
+    constexpr int WTM = Tl::WTM, WTN = Tl::WTN, ESZ = Tl::ESZ;
+    extern __shared__ __align__(16) uint8_t smem[];
 
     const int s = blockIdx.z;
     const int64_t b = blockIdx.y;
@@ -247,102 +300,171 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const int64_t tiles_m = (g.M + BM - 1) / BM;
     const int64_t t = xcd_tile(blockIdx.x, tiles_m * tiles_n);
     const int64_t m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
-    int shift = SCALE ? step_shift(sc, s) : 0;
-    if (SCALE && blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
+    int shift = step_shift(sc, s);
+    if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
     const float scale = pow2_neg(shift);
 
     const uint32_t *Ap = A + s * g.sA + b * g.bA;
     const uint32_t *Bp = B + s * g.sB + b * g.bB;
     uint32_t *Cp = C + s * g.sC + b * g.bC;
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
 
-    u32x4 ra[A_PER], rb[B_PER];
+    // ---- global loads: 16-byte chunks of 4 complex words
+    u32x4 ra[Tl::A_PER], rb[Tl::B_PER];
     auto gload = [&](int64_t k0) {
 #pragma unroll
-        for (int i = 0; i < A_PER; i++) {
+        for (int i = 0; i < Tl::A_PER; i++) {
             int c = tid + i * NT;
             u32x4 v = {0u, 0u, 0u, 0u};
-            if (c < A_CHUNKS) {
-                int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
-                int64_t gm = m0 + row, gk = k0 + col;
-                if (gm < g.M && gk < g.K) v = *(const u32x4 *)(Ap + gm * g.K + gk);
+            if (c < Tl::A_CHUNKS) {
+                if (g.a_kc) {
+                    int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
+                    int64_t gm = m0 + row, gk = k0 + col;
+                    if (gm < g.M && gk < g.K) v = *(const u32x4 *)(Ap + gm * g.K + gk);
+                } else {
+                    int kr = c / (BM / 4), mc = (c % (BM / 4)) * 4;
+                    int64_t gk = k0 + kr, gm = m0 + mc;
+                    if (gk < g.K && gm < g.M) v = *(const u32x4 *)(Ap + gk * g.M + gm);
+                }
             }
             ra[i] = v;
         }
 #pragma unroll
-        for (int i = 0; i < B_PER; i++) {
+        for (int i = 0; i < Tl::B_PER; i++) {
             int c = tid + i * NT;
             u32x4 v = {0u, 0u, 0u, 0u};
-            if (c < B_CHUNKS) {
-                int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
-                int64_t gn = n0 + row, gk = k0 + col;
-                if (gn < g.N && gk < g.K) v = *(const u32x4 *)(Bp + gn * g.K + gk);
+            if (c < Tl::B_CHUNKS) {
+                if (g.b_kc) {
+                    int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
+                    int64_t gn = n0 + row, gk = k0 + col;
+                    if (gn < g.N && gk < g.K) v = *(const u32x4 *)(Bp + gn * g.K + gk);
+                } else {
+                    int kr = c / (BN / 4), nc = (c % (BN / 4)) * 4;
+                    int64_t gk = k0 + kr, gn = n0 + nc;
+                    if (gk < g.K && gn < g.N) v = *(const u32x4 *)(Bp + gk * g.N + gn);
+                }
             }
             rb[i] = v;
         }
     };
+    // ---- LDS stores (row = m or n, col = k)
+    auto a_base = [&](int buf) { return smem + buf * (Tl::A_ELEMS * ESZ); };
+    auto b_base = [&](int buf) { return smem + 2 * Tl::A_ELEMS * ESZ + buf * (Tl::B_ELEMS * ESZ); };
+    auto put = [&](uint8_t *base, int rows, int ld, int row, int col, uint32_t w) {
+        if constexpr (M3) {
+            uint16_t *p = (uint16_t *)base;
+            p[row * ld + col] = (uint16_t)(w & 0xffffu);                    // re plane
+            p[rows * ld + row * ld + col] = (uint16_t)(w >> 16);            // im plane
+            p[2 * rows * ld + row * ld + col] = (uint16_t)sum_bits<BF>(w);  // sum plane
+        } else {
+            ((uint32_t *)base)[row * ld + col] = w;
+        }
+    };
+    auto put4 = [&](uint8_t *base, int rows, int ld, int row, int col, u32x4 v) {
+        if constexpr (M3) {
+            uint16_t *p = (uint16_t *)base;
+            u32x2 re = {(v[0] & 0xffffu) | (v[1] << 16), (v[2] & 0xffffu) | (v[3] << 16)};
+            u32x2 im = {(v[0] >> 16) | (v[1] & 0xffff0000u), (v[2] >> 16) | (v[3] & 0xffff0000u)};
+            u32x2 sm = {sum_bits<BF>(v[0]) | (sum_bits<BF>(v[1]) << 16), sum_bits<BF>(v[2]) | (sum_bits<BF>(v[3]) << 16)};
+            *(u32x2 *)(p + row * ld + col) = re;
+            *(u32x2 *)(p + rows * ld + row * ld + col) = im;
+            *(u32x2 *)(p + 2 * rows * ld + row * ld + col) = sm;
+        } else {
+            *(u32x4 *)((uint32_t *)base + row * ld + col) = v;
+        }
+    };
     auto sstore = [&](int buf) {
+        uint8_t *ab = a_base(buf), *bb = b_base(buf);
 #pragma unroll
-        for (int i = 0; i < A_PER; i++) {
+        for (int i = 0; i < Tl::A_PER; i++) {
             int c = tid + i * NT;
-            if (c < A_CHUNKS) {
-                int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
-                *(u32x4 *)(As(buf) + row * LDA + col) = ra[i];
+            if (c < Tl::A_CHUNKS) {
+                if (g.a_kc) {
+                    put4(ab, BM, LDA, c / (BK / 4), (c % (BK / 4)) * 4, ra[i]);
+                } else {
+                    int kr = c / (BM / 4), mc = (c % (BM / 4)) * 4;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) put(ab, BM, LDA, mc + q, kr, ra[i][q]);
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < B_PER; i++) {
+        for (int i = 0; i < Tl::B_PER; i++) {
             int c = tid + i * NT;
-            if (c < B_CHUNKS) {
-                int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
-                *(u32x4 *)(Bs(buf) + row * LDB + col) = rb[i];
+            if (c < Tl::B_CHUNKS) {
+                if (g.b_kc) {
+                    put4(bb, BN, LDB, c / (BK / 4), (c % (BK / 4)) * 4, rb[i]);
+                } else {
+                    int kr = c / (BN / 4), nc = (c % (BN / 4)) * 4;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) put(bb, BN, LDB, nc + q, kr, rb[i][q]);
+                }
             }
         }
     };
 
-    floatx16 acc[FM][FN];
+    constexpr int NACC = M3 ? 3 : 1;
+    floatx16 acc[NACC][FM][FN];
 #pragma unroll
-    for (int i = 0; i < FM; i++)
+    for (int a = 0; a < NACC; a++)
 #pragma unroll
-        for (int j = 0; j < FN; j++)
+        for (int i = 0; i < FM; i++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+            for (int j = 0; j < FN; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) acc[a][i][j][r] = 0.f;
 
     const int64_t nk = (g.K + BK - 1) / BK;
     gload(0);
     sstore(0);
     __syncthreads();
-    const int kq = (lane >> 5) * 4;     // this lane's 4 complex k within an 8-complex MFMA step
-    const int d = lane & 1;             // B' column parity: 0 -> (br, -bi), 1 -> (bi, br)
     for (int64_t kt = 0; kt < nk; kt++) {
         const int buf = kt & 1;
         if (kt + 1 < nk) gload((kt + 1) * BK);
+        const uint8_t *ab = a_base(buf), *bb = b_base(buf);
 #pragma unroll
-        for (int kk = 0; kk < BK / 8; kk++) {
-            u32x4 af[FM], bf[FN];
+        for (int kk = 0; kk < BK / Tl::KSTEP; kk++) {
+            if constexpr (!M3) {
+                const uint32_t *As = (const uint32_t *)ab, *Bs = (const uint32_t *)bb;
+                const int kq = kk * 8 + (lane >> 5) * 4;
+                const int d = lane & 1;
+                u32x4 af[FM], bf[FN];
 #pragma unroll
-            for (int i = 0; i < FM; i++) {
-                int row = wm * WTM + i * 32 + (lane & 31);
-                af[i] = *(const u32x4 *)(As(buf) + row * LDA + kk * 8 + kq);
-            }
+                for (int i = 0; i < FM; i++) af[i] = *(const u32x4 *)(As + (wm * WTM + i * 32 + (lane & 31)) * LDA + kq);
 #pragma unroll
-            for (int j = 0; j < FN; j++) {
-                int ncol = (wn * WTN + j * 32 + (lane & 31)) >> 1;
-                u32x4 v = *(const u32x4 *)(Bs(buf) + ncol * LDB + kk * 8 + kq);
-                if (d == 0) {
-                    v[0] ^= 0x80000000u; v[1] ^= 0x80000000u; v[2] ^= 0x80000000u; v[3] ^= 0x80000000u;
-                } else {
-                    v[0] = swap_halves(v[0]); v[1] = swap_halves(v[1]);
-                    v[2] = swap_halves(v[2]); v[3] = swap_halves(v[3]);
+                for (int j = 0; j < FN; j++) {
+                    u32x4 v = *(const u32x4 *)(Bs + ((wn * WTN + j * 32 + (lane & 31)) >> 1) * LDB + kq);
+                    if (d == 0) {   // (br, -bi)
+                        v[0] ^= 0x80000000u; v[1] ^= 0x80000000u; v[2] ^= 0x80000000u; v[3] ^= 0x80000000u;
+                    } else {        // (bi, br)
+                        v[0] = swap_halves(v[0]); v[1] = swap_halves(v[1]);
+                        v[2] = swap_halves(v[2]); v[3] = swap_halves(v[3]);
+                    }
+                    bf[j] = v;
                 }
-                bf[j] = v;
+#pragma unroll
+                for (int i = 0; i < FM; i++)
+#pragma unroll
+                    for (int j = 0; j < FN; j++) acc[0][i][j] = mfma16<BF>(af[i], bf[j], acc[0][i][j]);
+            } else {
+                const uint16_t *As = (const uint16_t *)ab, *Bs = (const uint16_t *)bb;
+                const int kq = kk * 16 + (lane >> 5) * 8;
+#pragma unroll
+                for (int p = 0; p < 3; p++) {
+                    u32x4 af[FM], bf[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; i++)
+                        af[i] = *(const u32x4 *)(As + p * BM * LDA + (wm * WTM + i * 32 + (lane & 31)) * LDA + kq);
+#pragma unroll
+                    for (int j = 0; j < FN; j++)
+                        bf[j] = *(const u32x4 *)(Bs + p * BN * LDB + (wn * WTN + j * 32 + (lane & 31)) * LDB + kq);
+#pragma unroll
+                    for (int i = 0; i < FM; i++)
+#pragma unroll
+                        for (int j = 0; j < FN; j++) acc[p][i][j] = mfma16<BF>(af[i], bf[j], acc[p][i][j]);
+                }
             }
-#pragma unroll
-            for (int i = 0; i < FM; i++)
-#pragma unroll
-                for (int j = 0; j < FN; j++) acc[i][j] = mfma16<BF>(af[i], bf[j], acc[i][j]);
         }
         __syncthreads();
         if (kt + 1 < nk) {
@@ -351,40 +473,64 @@ __global__ void __launch_bounds__(64 * WM * WN)
         }
     }
 
-    // epilogue: scale, round, stage the tile in LDS as complex words, write rows out
-    uint16_t *Cs = (uint16_t *)lds;   // [BM][2*BN] halves
+    // ---- epilogue: scale, round, stage the tile as complex words [BM][BN], write out
+    uint32_t *Cw = (uint32_t *)smem;
+    if constexpr (!M3) {
+        uint16_t *Ch = (uint16_t *)smem;
 #pragma unroll
-    for (int i = 0; i < FM; i++)
+        for (int i = 0; i < FM; i++)
 #pragma unroll
-        for (int j = 0; j < FN; j++)
+            for (int j = 0; j < FN; j++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                int col = wn * WTN + j * 32 + (lane & 31);   // real column 2n + part
-                float v = acc[i][j][r];
-                if (SCALE) v *= scale;
-                uint32_t h = BF ? f2bf_bits(v) : f2h_bits(v);
-                Cs[row * (2 * BN) + col] = (uint16_t)h;
-            }
+                for (int r = 0; r < 16; r++) {
+                    int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    int col = wn * WTN + j * 32 + (lane & 31);   // real column 2n + part
+                    float v = acc[0][i][j][r] * scale;
+                    Ch[row * (2 * BN) + col] = (uint16_t)(BF ? f2bf_bits(v) : f2h_bits(v));
+                }
+    } else {
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+            for (int j = 0; j < FN; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    int col = wn * WTN + j * 32 + (lane & 31);   // complex column
+                    float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+                    float re = (t1 - t2) * scale, im = (t3 - t1 - t2) * scale;
+                    Cw[row * BN + col] = Pack<W>::make(re, im).w;
+                }
+    }
     __syncthreads();
     float mx = 0.f;
     constexpr int C_CHUNKS = BM * BN / 4;
     for (int c = tid; c < C_CHUNKS; c += NT) {
-        int row = c / (BN / 4), col = (c % (BN / 4)) * 4;
-        int64_t gm = m0 + row, gn = n0 + col;
-        u32x4 v = *(const u32x4 *)(lds + row * BN + col);
-        if (gm < g.M && gn < g.N) {
-            *(u32x4 *)(Cp + gm * g.N + gn) = v;
-            if (SCALE) {
+        u32x4 v;
+        int64_t off;
+        bool ok;
+        if (g.c_nc) {
+            int row = c / (BN / 4), col = (c % (BN / 4)) * 4;
+            v = *(const u32x4 *)(Cw + row * BN + col);
+            ok = (m0 + row) < g.M && (n0 + col) < g.N;
+            off = (m0 + row) * g.N + n0 + col;
+        } else {
+            int col = c / (BM / 4), row = (c % (BM / 4)) * 4;
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    float2 f = unpack(W{v[q]});
-                    mx = fmaxf(mx, absmax_nan(f.x, f.y));
-                }
+            for (int q = 0; q < 4; q++) v[q] = Cw[(row + q) * BN + col];
+            ok = (m0 + row) < g.M && (n0 + col) < g.N;
+            off = (n0 + col) * g.M + m0 + row;
+        }
+        if (ok) {
+            *(u32x4 *)(Cp + off) = v;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                float2 f = unpack(W{v[q]});
+                mx = fmaxf(mx, absmax_nan(f.x, f.y));
             }
         }
     }
-    finish_max<SCALE>(sc, s, mx);
+    finish_max<true>(sc, s, mx);
 }
 
 // ===================================================================== matrix cores, complex64 4M
@@ -392,19 +538,29 @@ __global__ void __launch_bounds__(64 * WM * WN)
 // one MFMA per complex k (k' = 2k + c).
 
 template <int BM, int BN, int BK, int WM, int WN>
+struct CTile {
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int LDA = BK + 1, LDB = BK + 1;
+    static constexpr int AB = 2 * (BM * LDA + BN * LDB) * 8;
+    static constexpr int CB = BM * BN * 8;
+    static constexpr int LDS_BYTES = AB > CB ? AB : CB;
+    static constexpr int WTM = BM / WM, WTN = 2 * BN / WN;
+    static constexpr int FM = WTM / 32, FN = WTN / 32;
+    static constexpr int A_CHUNKS = BM * BK / 2, B_CHUNKS = BN * BK / 2;   // 16-byte chunks (2 complex)
+    static constexpr int A_PER = (A_CHUNKS + NT - 1) / NT, B_PER = (B_CHUNKS + NT - 1) / NT;
+    static_assert(FM >= 1 && FN >= 1, "wave tile too small");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+template <int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
     gemm_mfma_c64_kernel(const float2 *__restrict__ A, const float2 *__restrict__ B, float2 *__restrict__ C,
                          GemmShape g) {
-    constexpr int NT = 64 * WM * WN;
-    constexpr int LDA = BK + 1, LDB = BK + 1;
-    constexpr int WTM = BM / WM, WTN = 2 * BN / WN;
-    constexpr int FM = WTM / 32, FN = WTN / 32;
-    static_assert(FM >= 1 && FN >= 1, "wave tile too small");
-    constexpr int A_CHUNKS = BM * BK / 2, B_CHUNKS = BN * BK / 2;   // 16-byte chunks (2 complex)
-    constexpr int A_PER = (A_CHUNKS + NT - 1) / NT, B_PER = (B_CHUNKS + NT - 1) / NT;
-    constexpr int LDS_AB = 2 * (BM * LDA + BN * LDB);
-    constexpr int LDS_C = BM * BN;
-    __shared__ float2 lds[LDS_AB > LDS_C ? LDS_AB : LDS_C];
+    using Tl = CTile<BM, BN, BK, WM, WN>;
+    constexpr int NT = Tl::NT, LDA = Tl::LDA, LDB = Tl::LDB, FM = Tl::FM, FN = Tl::FN;
+    constexpr int WTM = Tl::WTM, WTN = Tl::WTN;
+    extern __shared__ __align__(16) uint8_t smem[];
+    float2 *lds = (float2 *)smem;
     auto As = [&](int buf) { return lds + buf * (BM * LDA); };
     auto Bs = [&](int buf) { return lds + 2 * BM * LDA + buf * (BN * LDB); };
 
@@ -420,48 +576,73 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
 
-    float4 ra[A_PER], rb[B_PER];
+    float4 ra[Tl::A_PER], rb[Tl::B_PER];
     auto gload = [&](int64_t k0) {
 #pragma unroll
-        for (int i = 0; i < A_PER; i++) {
+        for (int i = 0; i < Tl::A_PER; i++) {
             int c = tid + i * NT;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < A_CHUNKS) {
-                int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
-                int64_t gm = m0 + row, gk = k0 + col;
-                if (gm < g.M && gk < g.K) v = *(const float4 *)(Ap + gm * g.K + gk);
+            if (c < Tl::A_CHUNKS) {
+                if (g.a_kc) {
+                    int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
+                    int64_t gm = m0 + row, gk = k0 + col;
+                    if (gm < g.M && gk < g.K) v = *(const float4 *)(Ap + gm * g.K + gk);
+                } else {
+                    int kr = c / (BM / 2), mc = (c % (BM / 2)) * 2;
+                    int64_t gk = k0 + kr, gm = m0 + mc;
+                    if (gk < g.K && gm < g.M) v = *(const float4 *)(Ap + gk * g.M + gm);
+                }
             }
             ra[i] = v;
         }
 #pragma unroll
-        for (int i = 0; i < B_PER; i++) {
+        for (int i = 0; i < Tl::B_PER; i++) {
             int c = tid + i * NT;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < B_CHUNKS) {
-                int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
-                int64_t gn = n0 + row, gk = k0 + col;
-                if (gn < g.N && gk < g.K) v = *(const float4 *)(Bp + gn * g.K + gk);
+            if (c < Tl::B_CHUNKS) {
+                if (g.b_kc) {
+                    int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
+                    int64_t gn = n0 + row, gk = k0 + col;
+                    if (gn < g.N && gk < g.K) v = *(const float4 *)(Bp + gn * g.K + gk);
+                } else {
+                    int kr = c / (BN / 2), nc = (c % (BN / 2)) * 2;
+                    int64_t gk = k0 + kr, gn = n0 + nc;
+                    if (gk < g.K && gn < g.N) v = *(const float4 *)(Bp + gk * g.N + gn);
+                }
             }
             rb[i] = v;
         }
     };
     auto sstore = [&](int buf) {
+        float2 *a = As(buf), *bb = Bs(buf);
 #pragma unroll
-        for (int i = 0; i < A_PER; i++) {
+        for (int i = 0; i < Tl::A_PER; i++) {
             int c = tid + i * NT;
-            if (c < A_CHUNKS) {
-                int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
-                As(buf)[row * LDA + col] = make_float2(ra[i].x, ra[i].y);
-                As(buf)[row * LDA + col + 1] = make_float2(ra[i].z, ra[i].w);
+            if (c < Tl::A_CHUNKS) {
+                if (g.a_kc) {
+                    int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
+                    a[row * LDA + col] = make_float2(ra[i].x, ra[i].y);
+                    a[row * LDA + col + 1] = make_float2(ra[i].z, ra[i].w);
+                } else {
+                    int kr = c / (BM / 2), mc = (c % (BM / 2)) * 2;
+                    a[mc * LDA + kr] = make_float2(ra[i].x, ra[i].y);
+                    a[(mc + 1) * LDA + kr] = make_float2(ra[i].z, ra[i].w);
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < B_PER; i++) {
+        for (int i = 0; i < Tl::B_PER; i++) {
             int c = tid + i * NT;
-            if (c < B_CHUNKS) {
-                int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
-                Bs(buf)[row * LDB + col] = make_float2(rb[i].x, rb[i].y);
-                Bs(buf)[row * LDB + col + 1] = make_float2(rb[i].z, rb[i].w);
+            if (c < Tl::B_CHUNKS) {
+                if (g.b_kc) {
+                    int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
+                    bb[row * LDB + col] = make_float2(rb[i].x, rb[i].y);
+                    bb[row * LDB + col + 1] = make_float2(rb[i].z, rb[i].w);
+                } else {
+                    int kr = c / (BN / 2), nc = (c % (BN / 2)) * 2;
+                    bb[nc * LDB + kr] = make_float2(rb[i].x, rb[i].y);
+                    bb[(nc + 1) * LDB + kr] = make_float2(rb[i].z, rb[i].w);
+                }
             }
         }
     };
@@ -483,17 +664,18 @@ __global__ void __launch_bounds__(64 * WM * WN)
     for (int64_t kt = 0; kt < nk; kt++) {
         const int buf = kt & 1;
         if (kt + 1 < nk) gload((kt + 1) * BK);
+        const float2 *a = As(buf), *bb = Bs(buf);
 #pragma unroll 4
         for (int kk = 0; kk < BK; kk++) {
             float af[FM], bf[FN];
 #pragma unroll
             for (int i = 0; i < FM; i++) {
-                float2 v = As(buf)[(wm * WTM + i * 32 + (lane & 31)) * LDA + kk];
+                float2 v = a[(wm * WTM + i * 32 + (lane & 31)) * LDA + kk];
                 af[i] = c ? v.y : v.x;
             }
 #pragma unroll
             for (int j = 0; j < FN; j++) {
-                float2 v = Bs(buf)[((wn * WTN + j * 32 + (lane & 31)) >> 1) * LDB + kk];
+                float2 v = bb[((wn * WTN + j * 32 + (lane & 31)) >> 1) * LDB + kk];
                 // B'[2k+c][2n+d]: (c,d) = (0,0) br, (1,0) -bi, (0,1) bi, (1,1) br
                 bf[j] = (c == d) ? v.x : (c ? -v.y : v.y);
             }
@@ -509,7 +691,7 @@ __global__ void __launch_bounds__(64 * WM * WN)
             __syncthreads();
         }
     }
-    float *Cs = (float *)lds;   // [BM][2*BN]
+    float *Cs = (float *)smem;   // [BM][2*BN]
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
@@ -523,9 +705,19 @@ __global__ void __launch_bounds__(64 * WM * WN)
     __syncthreads();
     constexpr int C_CHUNKS = BM * BN / 2;
     for (int cc = tid; cc < C_CHUNKS; cc += NT) {
-        int row = cc / (BN / 2), col = (cc % (BN / 2)) * 2;
-        int64_t gm = m0 + row, gn = n0 + col;
-        if (gm < g.M && gn < g.N) *(float4 *)(Cp + gm * g.N + gn) = *(const float4 *)(Cs + row * 2 * BN + 2 * col);
+        if (g.c_nc) {
+            int row = cc / (BN / 2), col = (cc % (BN / 2)) * 2;
+            int64_t gm = m0 + row, gn = n0 + col;
+            if (gm < g.M && gn < g.N) *(float4 *)(Cp + gm * g.N + gn) = *(const float4 *)(Cs + row * 2 * BN + 2 * col);
+        } else {
+            int col = cc / (BM / 2), row = (cc % (BM / 2)) * 2;
+            int64_t gm = m0 + row, gn = n0 + col;
+            if (gm < g.M && gn < g.N) {
+                float2 v0 = *(const float2 *)(Cs + row * 2 * BN + 2 * col);
+                float2 v1 = *(const float2 *)(Cs + (row + 1) * 2 * BN + 2 * col);
+                *(float4 *)(Cp + gn * g.M + gm) = make_float4(v0.x, v0.y, v1.x, v1.y);
+            }
+        }
     }
 }
 
@@ -535,31 +727,48 @@ const char *kernel_name(int k) {
     switch (k) {
         case K_NAIVE: return "naive";
         case K_SKINNY_N: return "skinny";
-        case K_MFMA_S: return "mfma_64x16";
-        case K_MFMA_M: return "mfma_128x32";
-        case K_MFMA_L: return "mfma_128x64";
-        case K_MFMA_W: return "mfma_256x16";
+        case K_MFMA_S: return "mfma_s";
+        case K_MFMA_M: return "mfma_m";
+        case K_MFMA_L: return "mfma_l";
+        case K_MFMA_W: return "mfma_w";
+        case K_MFMA_XL: return "mfma_xl";
+        case K_MFMA_L2: return "mfma_l2";
         default: return "?";
     }
 }
 
+// block tile (rows, complex columns) of each matrix-core variant
 struct TileCfg {
     int BM, BN;
 };
-static TileCfg tile_of(int kid, Dtype dt) {
+static TileCfg tile_of(int kid, Dtype dt, Algo al) {
     if (dt == Dtype::C64) {
         switch (kid) {
             case K_MFMA_S: return {64, 16};
             case K_MFMA_M: return {128, 16};
             case K_MFMA_L: return {128, 32};
             case K_MFMA_W: return {256, 16};
+            case K_MFMA_XL: return {128, 64};
+            case K_MFMA_L2: return {256, 32};
         }
-    }
-    switch (kid) {
-        case K_MFMA_S: return {64, 16};
-        case K_MFMA_M: return {128, 32};
-        case K_MFMA_L: return {128, 64};
-        case K_MFMA_W: return {256, 16};
+    } else if (al == Algo::M4) {
+        switch (kid) {
+            case K_MFMA_S: return {64, 16};
+            case K_MFMA_M: return {128, 32};
+            case K_MFMA_L: return {128, 64};
+            case K_MFMA_W: return {256, 16};
+            case K_MFMA_XL: return {256, 128};
+            case K_MFMA_L2: return {128, 128};
+        }
+    } else {
+        switch (kid) {
+            case K_MFMA_S: return {64, 32};
+            case K_MFMA_M: return {128, 64};
+            case K_MFMA_L: return {128, 128};
+            case K_MFMA_W: return {256, 32};
+            case K_MFMA_XL: return {256, 64};
+            case K_MFMA_L2: return {128, 32};
+        }
     }
     return {0, 0};
 }
@@ -573,12 +782,16 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
     }
     if (g.nb > 65535) return false;
     if (kid < 0 || kid >= K_COUNT) return false;
-    if (al == Algo::M3) return false;           // 3M runs on the VALU kernels
-    TileCfg t = tile_of(kid, dt);
-    // matrix-core tiles need whole 16-byte chunks along K and whole tiles along M, N
-    const int64_t kmin = dt == Dtype::C64 ? 2 : 8;
-    if (g.K < kmin) return false;
+    if (dt == Dtype::C64 && al == Algo::M3) return false;
+    TileCfg t = tile_of(kid, dt, al);
+    // whole 16-byte chunks along every contiguous dimension, whole tiles along M and N
+    const int64_t q = dt == Dtype::C64 ? 2 : 4;
+    if (g.K < q || g.K % q) return false;
+    if (!g.a_kc && g.M % q) return false;
+    if (!g.b_kc && g.N % q) return false;
+    if (dt != Dtype::C64 && g.K < 8) return false;
     if (g.M < t.BM || g.N < t.BN) return false;
+    if (g.M % t.BM || g.N % t.BN) return false;
     return true;
 }
 
@@ -597,7 +810,6 @@ static void launch_valu(int kid, Algo al, const void *A, const void *B, void *C,
                                (const W *)B, (W *)C, g, sc);
         return;
     }
-    // skinny: choose NN = min(N, 16) rounded to a power of two
     int64_t nn = g.N < 16 ? g.N : 16;
     int64_t nch = (g.N + nn - 1) / nn;
     dim3 grid((unsigned)((g.M + 255) / 256), (unsigned)(g.nb * nch), S);
@@ -620,51 +832,69 @@ static void launch_valu(int kid, Algo al, const void *A, const void *B, void *C,
 #undef SKINNY
 }
 
-template <bool BF>
-static void launch_h4m(int kid, const void *A, const void *B, void *C, const GemmShape &g, int S,
-                       const ScaleRefs &sc, hipStream_t st) {
-    TileCfg t = tile_of(kid, BF ? Dtype::BF16 : Dtype::F16);
-    int64_t tiles = ((g.M + t.BM - 1) / t.BM) * ((g.N + t.BN - 1) / t.BN);
+template <bool BF, bool M3, int BM, int BN, int BK, int WM, int WN>
+static void launch_h_cfg(const void *A, const void *B, void *C, const GemmShape &g, int S, const ScaleRefs &sc,
+                         hipStream_t st) {
+    using Tl = HTile<BF, M3, BM, BN, BK, WM, WN>;
+    auto kern = gemm_mfma_h_kernel<BF, M3, BM, BN, BK, WM, WN>;
+    static bool attr = false;
+    if (!attr) {
+        HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, Tl::LDS_BYTES));
+        attr = true;
+    }
+    int64_t tiles = (g.M / BM) * (g.N / BN);
     dim3 grid((unsigned)tiles, (unsigned)g.nb, S);
-    auto a = (const uint32_t *)A;
-    auto b = (const uint32_t *)B;
-    auto c = (uint32_t *)C;
-    switch (kid) {
-        case K_MFMA_S:
-            hipLaunchKernelGGL((gemm_mfma_h4m_kernel<BF, 64, 16, 32, 2, 1, true>), grid, dim3(128), 0, st, a, b, c, g, sc);
-            break;
-        case K_MFMA_M:
-            hipLaunchKernelGGL((gemm_mfma_h4m_kernel<BF, 128, 32, 32, 2, 2, true>), grid, dim3(256), 0, st, a, b, c, g, sc);
-            break;
-        case K_MFMA_L:
-            hipLaunchKernelGGL((gemm_mfma_h4m_kernel<BF, 128, 64, 32, 2, 2, true>), grid, dim3(256), 0, st, a, b, c, g, sc);
-            break;
-        case K_MFMA_W:
-            hipLaunchKernelGGL((gemm_mfma_h4m_kernel<BF, 256, 16, 32, 4, 1, true>), grid, dim3(256), 0, st, a, b, c, g, sc);
-            break;
+    hipLaunchKernelGGL(kern, grid, dim3(Tl::NT), Tl::LDS_BYTES, st, (const uint32_t *)A, (const uint32_t *)B,
+                       (uint32_t *)C, g, sc);
+}
+
+template <bool BF>
+static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, const GemmShape &g, int S,
+                     const ScaleRefs &sc, hipStream_t st) {
+    if (al == Algo::M4) {
+        switch (kid) {
+            case K_MFMA_S: launch_h_cfg<BF, false, 64, 16, 32, 2, 1>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_M: launch_h_cfg<BF, false, 128, 32, 32, 2, 2>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_L: launch_h_cfg<BF, false, 128, 64, 32, 2, 2>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_W: launch_h_cfg<BF, false, 256, 16, 32, 4, 1>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_XL: launch_h_cfg<BF, false, 256, 128, 16, 2, 2>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_L2: launch_h_cfg<BF, false, 128, 128, 32, 2, 2>(A, B, C, g, S, sc, st); break;
+        }
+    } else {
+        switch (kid) {
+            case K_MFMA_S: launch_h_cfg<BF, true, 64, 32, 32, 2, 1>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_M: launch_h_cfg<BF, true, 128, 64, 32, 2, 2>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_L: launch_h_cfg<BF, true, 128, 128, 32, 2, 2>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_W: launch_h_cfg<BF, true, 256, 32, 32, 4, 1>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_XL: launch_h_cfg<BF, true, 256, 64, 32, 4, 1>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_L2: launch_h_cfg<BF, true, 128, 32, 32, 4, 1>(A, B, C, g, S, sc, st); break;
+        }
     }
 }
 
-static void launch_c64(int kid, const void *A, const void *B, void *C, const GemmShape &g, int S, hipStream_t st) {
-    TileCfg t = tile_of(kid, Dtype::C64);
-    int64_t tiles = ((g.M + t.BM - 1) / t.BM) * ((g.N + t.BN - 1) / t.BN);
+template <int BM, int BN, int BK, int WM, int WN>
+static void launch_c_cfg(const void *A, const void *B, void *C, const GemmShape &g, int S, hipStream_t st) {
+    using Tl = CTile<BM, BN, BK, WM, WN>;
+    auto kern = gemm_mfma_c64_kernel<BM, BN, BK, WM, WN>;
+    static bool attr = false;
+    if (!attr) {
+        HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, Tl::LDS_BYTES));
+        attr = true;
+    }
+    int64_t tiles = (g.M / BM) * (g.N / BN);
     dim3 grid((unsigned)tiles, (unsigned)g.nb, S);
-    auto a = (const float2 *)A;
-    auto b = (const float2 *)B;
-    auto c = (float2 *)C;
+    hipLaunchKernelGGL(kern, grid, dim3(Tl::NT), Tl::LDS_BYTES, st, (const float2 *)A, (const float2 *)B,
+                       (float2 *)C, g);
+}
+
+static void launch_c64(int kid, const void *A, const void *B, void *C, const GemmShape &g, int S, hipStream_t st) {
     switch (kid) {
-        case K_MFMA_S:
-            hipLaunchKernelGGL((gemm_mfma_c64_kernel<64, 16, 16, 2, 1>), grid, dim3(128), 0, st, a, b, c, g);
-            break;
-        case K_MFMA_M:
-            hipLaunchKernelGGL((gemm_mfma_c64_kernel<128, 16, 16, 4, 1>), grid, dim3(256), 0, st, a, b, c, g);
-            break;
-        case K_MFMA_L:
-            hipLaunchKernelGGL((gemm_mfma_c64_kernel<128, 32, 16, 2, 2>), grid, dim3(256), 0, st, a, b, c, g);
-            break;
-        case K_MFMA_W:
-            hipLaunchKernelGGL((gemm_mfma_c64_kernel<256, 16, 16, 4, 1>), grid, dim3(256), 0, st, a, b, c, g);
-            break;
+        case K_MFMA_S: launch_c_cfg<64, 16, 16, 2, 1>(A, B, C, g, S, st); break;
+        case K_MFMA_M: launch_c_cfg<128, 16, 16, 4, 1>(A, B, C, g, S, st); break;
+        case K_MFMA_L: launch_c_cfg<128, 32, 16, 2, 2>(A, B, C, g, S, st); break;
+        case K_MFMA_W: launch_c_cfg<256, 16, 16, 4, 1>(A, B, C, g, S, st); break;
+        case K_MFMA_XL: launch_c_cfg<128, 64, 16, 2, 2>(A, B, C, g, S, st); break;
+        case K_MFMA_L2: launch_c_cfg<256, 32, 16, 2, 2>(A, B, C, g, S, st); break;
     }
 }
 
@@ -674,6 +904,7 @@ void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void 
     if (!gemm_supported(kid, dt, al, g)) TNC_THROW(TNC_EINVAL, std::string("kernel ") + kernel_name(kid) + " cannot run this shape");
     ScaleRefs none{};
     const ScaleRefs &s = sc ? *sc : none;
+    if (dt != Dtype::C64 && !sc) TNC_THROW(TNC_EINVAL, "16-bit forms need scale bookkeeping");
     if (kid == K_NAIVE || kid == K_SKINNY_N) {
         if (dt == Dtype::C64)
             launch_valu<uint2, false>(kid, al, A, B, C, g, S, s, st);
@@ -684,9 +915,9 @@ void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void 
     } else if (dt == Dtype::C64) {
         launch_c64(kid, A, B, C, g, S, st);
     } else if (dt == Dtype::F16) {
-        launch_h4m<false>(kid, A, B, C, g, S, s, st);
+        launch_h<false>(kid, al, A, B, C, g, S, s, st);
     } else {
-        launch_h4m<true>(kid, A, B, C, g, S, s, st);
+        launch_h<true>(kid, al, A, B, C, g, S, s, st);
     }
     HIP_CHECK(hipGetLastError());
 }

@@ -75,12 +75,13 @@ static std::vector<int> extract(const std::vector<int> &order, const std::vector
 }
 
 int choose_kernel(Dtype dt, Algo al, const GemmShape &g) {
-    if (al == Algo::M4) {
-        if (g.N >= 64 && g.M >= 128 && gemm_supported(K_MFMA_L, dt, al, g)) return K_MFMA_L;
-        if (g.N >= 32 && g.M >= 128 && gemm_supported(K_MFMA_M, dt, al, g)) return K_MFMA_M;
-        if (g.N >= 16 && g.M >= 256 && gemm_supported(K_MFMA_W, dt, al, g)) return K_MFMA_W;
-        if (gemm_supported(K_MFMA_S, dt, al, g)) return K_MFMA_S;
-    }
+    // largest matrix-core tile that divides the shape, once the step has
+    // enough work for more than a handful of tiles; thin steps go to the VALU
+    static const int order[] = {K_MFMA_XL, K_MFMA_L2, K_MFMA_L, K_MFMA_M, K_MFMA_W, K_MFMA_S};
+    const double work = (double)g.M * (double)g.N * (double)g.K;
+    if (work >= 1 << 18 && (g.N >= 16 || al == Algo::M3))
+        for (int k : order)
+            if (gemm_supported(k, dt, al, g)) return k;
     if (gemm_supported(K_SKINNY_N, dt, al, g)) return K_SKINNY_N;
     return K_NAIVE;
 }
@@ -209,100 +210,148 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         if (cnt != n_open) TNC_THROW(TNC_EINVAL, "an open output label never reaches the root");
     }
 
-    // layout pass: storage orders and permutes
+    // layout pass: storage orders, operand orientations and permutes
     const int es = elem_bytes(an.dt);
     for (int s = 0; s < n_steps; s++) {
         StepRec &st = an.steps[s];
         TensorRec &A = an.tensors[st.a], &B = an.tensors[st.b], &Z = an.tensors[st.z];
-        // consumer preference of Z's labels: 0 batch, 1 free, 2 contracted there
-        std::vector<int> pref(L, 1);
+        // consumer groups of Z's labels: 0 batch, 1 kept free, 2 contracted there
+        std::vector<int> cg(L, 1);
         if (Z.consumer >= 0) {
             const StepRec &c = an.steps[Z.consumer];
-            for (int l : c.beta) pref[l] = 0;
-            for (int l : c.k) pref[l] = 2;
+            for (int l : c.beta) cg[l] = 0;
+            for (int l : c.k) cg[l] = 2;
         }
-        auto by_pref = [&](std::vector<int> v) {
-            std::stable_sort(v.begin(), v.end(), [&](int p, int q) { return pref[p] < pref[q]; });
-            return v;
-        };
-        // group ids for A: 0 batch, 1 m, 2 k ; for B: 0 batch, 1 n, 2 k
         for (int l : st.beta) grp[l] = 0;
         for (int l : st.m) grp[l] = 1;
         for (int l : st.n) grp[l] = 1;
         for (int l : st.k) grp[l] = 2;
         std::vector<int> sa = {(int)st.beta.size(), (int)st.m.size(), (int)st.k.size()};
         std::vector<int> sb = {(int)st.beta.size(), (int)st.n.size(), (int)st.k.size()};
-        bool a_ok = !A.leaf && has_pattern(A.labels, grp, sa);
-        bool b_ok = !B.leaf && has_pattern(B.labels, grp, sb);
-        // the batch and k orders must agree between A and B; take them from an
-        // operand that keeps its layout, preferring the larger one
-        std::vector<int> beta_o, k_o;
-        const double szA = std::ldexp(1.0, A.rank()), szB = std::ldexp(1.0, B.rank());
-        auto cost_with = [&](const std::vector<int> &bo, const std::vector<int> &ko) {
-            double c = 0;
-            if (!A.leaf && !(a_ok && extract(A.labels, grp, 0) == bo && extract(A.labels, grp, 2) == ko)) c += szA;
-            if (!B.leaf && !(b_ok && extract(B.labels, grp, 0) == bo && extract(B.labels, grp, 2) == ko)) c += szB;
-            return c;
+        // an operand fits as [batch][free][k] (K-contiguous) or [batch][k][free]
+        auto orient = [&](const TensorRec &T, const std::vector<int> &sz) -> int {
+            if (T.leaf) return -1;
+            if (has_pattern(T.labels, grp, sz)) return 1;
+            std::vector<int> g2(grp);
+            for (int l : T.labels) g2[l] = grp[l] == 1 ? 2 : (grp[l] == 2 ? 1 : grp[l]);
+            std::vector<int> sz2 = {sz[0], sz[2], sz[1]};
+            if (has_pattern(T.labels, g2, sz2)) return 0;
+            return -1;
         };
-        std::vector<std::pair<std::vector<int>, std::vector<int>>> cands;
-        if (a_ok) cands.push_back({extract(A.labels, grp, 0), extract(A.labels, grp, 2)});
-        if (b_ok) cands.push_back({extract(B.labels, grp, 0), extract(B.labels, grp, 2)});
-        if (cands.empty()) {
-            std::vector<int> bo = extract(A.labels, grp, 0), ko = extract(A.labels, grp, 2);
-            if (A.leaf && !B.leaf) {
-                bo = extract(B.labels, grp, 0);
-                ko = extract(B.labels, grp, 2);
-            }
-            cands.push_back({bo, ko});
-        }
-        double best = 1e300;
-        for (auto &c : cands) {
-            double v = cost_with(c.first, c.second);
-            if (v < best) {
-                best = v;
-                beta_o = c.first;
-                k_o = c.second;
+        int oa = orient(A, sa), ob = orient(B, sb);
+        const double szA = std::ldexp(1.0, A.rank()), szB = std::ldexp(1.0, B.rank());
+        // batch and k orders must agree between A and B; take them from a kept
+        // operand, preferring the larger
+        std::vector<int> beta_o, k_o;
+        bool keepA = oa >= 0, keepB = ob >= 0;
+        if (keepA && keepB) {
+            if (extract(A.labels, grp, 0) != extract(B.labels, grp, 0) ||
+                extract(A.labels, grp, 2) != extract(B.labels, grp, 2)) {
+                if (szA >= szB) keepB = false;
+                else keepA = false;
             }
         }
-        // A: keep, or reorder to [beta][m (consumer order)][k]
-        std::vector<int> m_o, n_o;
-        if (a_ok && extract(A.labels, grp, 0) == beta_o && extract(A.labels, grp, 2) == k_o) {
-            m_o = extract(A.labels, grp, 1);
+        if (keepA) {
+            beta_o = extract(A.labels, grp, 0);
+            k_o = extract(A.labels, grp, 2);
+        } else if (keepB) {
+            beta_o = extract(B.labels, grp, 0);
+            k_o = extract(B.labels, grp, 2);
         } else {
-            m_o = by_pref(extract(A.labels, grp, 1));
-            std::vector<int> want = beta_o;
-            want.insert(want.end(), m_o.begin(), m_o.end());
-            want.insert(want.end(), k_o.begin(), k_o.end());
-            if (A.leaf) {
-                A.labels = want;
-            } else {
+            const TensorRec &src = (!A.leaf || B.leaf) ? A : B;
+            beta_o = extract(src.labels, grp, 0);
+            k_o = extract(src.labels, grp, 2);
+        }
+        std::vector<int> m_o = extract(A.labels, grp, 1), n_o = extract(B.labels, grp, 1);
+        // Z order: try both C orientations and both consumer orientations; free
+        // internal orders (operands that are permuted or gathered) follow the
+        // consumer's groups
+        auto ranked = [&](std::vector<int> v, bool kfirst) {
+            std::stable_sort(v.begin(), v.end(), [&](int p, int q) {
+                auto key = [&](int l) { return cg[l] == 0 ? 0 : (kfirst ? (cg[l] == 2 ? 1 : 2) : cg[l]); };
+                return key(p) < key(q);
+            });
+            return v;
+        };
+        auto consumer_fits = [&](const std::vector<int> &zo) {
+            if (Z.consumer < 0) return true;
+            int last = -1;
+            bool inc = true, dec_ok = true;
+            // [0][1][2] or [0][2][1]
+            std::vector<int> key;
+            for (int l : zo) key.push_back(cg[l]);
+            for (int v : key) {
+                if (v < last) inc = false;
+                last = v;
+            }
+            last = -1;
+            for (int v : key) {
+                int w = v == 0 ? 0 : (v == 2 ? 1 : 2);
+                if (w < last) dec_ok = false;
+                last = w;
+            }
+            return inc || dec_ok;
+        };
+        std::vector<int> best_m = m_o, best_n = n_o;
+        int best_cnc = 1;
+        bool found = false;
+        for (int kfirst = 0; kfirst < 2 && !found; kfirst++) {
+            std::vector<int> mm = keepA ? m_o : ranked(m_o, kfirst), nn = keepB ? n_o : ranked(n_o, kfirst);
+            for (int cnc = 1; cnc >= 0 && !found; cnc--) {
+                std::vector<int> zo = beta_o;
+                const auto &x = cnc ? mm : nn;
+                const auto &y = cnc ? nn : mm;
+                zo.insert(zo.end(), x.begin(), x.end());
+                zo.insert(zo.end(), y.begin(), y.end());
+                if (consumer_fits(zo)) {
+                    best_m = mm;
+                    best_n = nn;
+                    best_cnc = cnc;
+                    found = true;
+                }
+            }
+        }
+        if (!found) {
+            best_m = keepA ? m_o : ranked(m_o, false);
+            best_n = keepB ? n_o : ranked(n_o, false);
+        }
+        m_o = best_m;
+        n_o = best_n;
+        // operand orders
+        auto cat3 = [](const std::vector<int> &a, const std::vector<int> &b, const std::vector<int> &c) {
+            std::vector<int> r = a;
+            r.insert(r.end(), b.begin(), b.end());
+            r.insert(r.end(), c.begin(), c.end());
+            return r;
+        };
+        if (keepA) {
+            st.a_kc = oa;
+        } else {
+            std::vector<int> want = cat3(beta_o, m_o, k_o);
+            if (!A.leaf) {
                 st.perm_a = true;
                 st.a_from = A.labels;
-                A.labels = want;   // the permuted copy is what the GEMM reads
             }
+            A.labels = want;
+            st.a_kc = 1;
         }
-        if (b_ok && extract(B.labels, grp, 0) == beta_o && extract(B.labels, grp, 2) == k_o) {
-            n_o = extract(B.labels, grp, 1);
+        if (keepB) {
+            st.b_kc = ob;
         } else {
-            n_o = by_pref(extract(B.labels, grp, 1));
-            std::vector<int> want = beta_o;
-            want.insert(want.end(), n_o.begin(), n_o.end());
-            want.insert(want.end(), k_o.begin(), k_o.end());
-            if (B.leaf) {
-                B.labels = want;
-            } else {
+            std::vector<int> want = cat3(beta_o, n_o, k_o);
+            if (!B.leaf) {
                 st.perm_b = true;
                 st.b_from = B.labels;
-                B.labels = want;
             }
+            B.labels = want;
+            st.b_kc = 1;
         }
+        st.c_nc = best_cnc;
         st.beta = beta_o;
         st.m = m_o;
         st.n = n_o;
         st.k = k_o;
-        Z.labels = beta_o;
-        Z.labels.insert(Z.labels.end(), m_o.begin(), m_o.end());
-        Z.labels.insert(Z.labels.end(), n_o.begin(), n_o.end());
+        Z.labels = st.c_nc ? cat3(beta_o, m_o, n_o) : cat3(beta_o, n_o, m_o);
         st.nb = (int64_t)1 << st.beta.size();
         st.M = (int64_t)1 << st.m.size();
         st.N = (int64_t)1 << st.n.size();
@@ -310,7 +359,12 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         st.flops = 8.0 * (double)st.nb * (double)st.M * (double)st.N * (double)st.K;
         st.bytes = es * (std::ldexp(1.0, A.rank()) + std::ldexp(1.0, B.rank()) + std::ldexp(1.0, Z.rank()));
         st.perm_bytes = (st.perm_a ? 2.0 * es * szA : 0.0) + (st.perm_b ? 2.0 * es * szB : 0.0);
+        st.hoist_a = st.perm_a && st.dep && !A.dep;
+        st.hoist_b = st.perm_b && st.dep && !B.dep;
         GemmShape g{st.M, st.N, st.K, st.nb, 0, 0, 0, st.M * st.K, st.N * st.K, st.M * st.N};
+        g.a_kc = st.a_kc;
+        g.b_kc = st.b_kc;
+        g.c_nc = st.c_nc;
         st.kernel = choose_kernel(an.dt, an.al, g);
         for (int l : st.beta) grp[l] = -1;
         for (int l : st.m) grp[l] = -1;
@@ -382,19 +436,32 @@ int64_t plan_memory(Analysis &an, int S, bool assign) {
     auto run_step = [&](int s) {
         StepRec &st = an.steps[s];
         const TensorRec &A = an.tensors[st.a], &B = an.tensors[st.b], &Z = an.tensors[st.z];
-        // operands of a dependent step that are invariant keep a single copy
-        if (st.perm_a) scr_a[s] = ar.alloc(bytes_of(A));
-        if (st.perm_b) scr_b[s] = ar.alloc(bytes_of(B));
+        const bool pa = st.perm_a && !st.hoist_a, pb = st.perm_b && !st.hoist_b;
+        if (pa) scr_a[s] = ar.alloc(bytes_of(A));
+        if (pb) scr_b[s] = ar.alloc(bytes_of(B));
         off[st.z] = ar.alloc(bytes_of(Z));
-        if (st.perm_a) ar.release(scr_a[s], bytes_of(A));
-        if (st.perm_b) ar.release(scr_b[s], bytes_of(B));
+        if (pa) ar.release(scr_a[s], bytes_of(A));
+        if (pb) ar.release(scr_b[s], bytes_of(B));
         for (int t : {st.a, st.b}) {
             const TensorRec &T = an.tensors[t];
-            if (T.dep == st.dep) ar.release(off[t], bytes_of(T));   // consumed
+            // an invariant operand of a dependent step is read by every group: kept
+            if (T.dep == st.dep) ar.release(off[t], bytes_of(T));
         }
     };
     for (int s = 0; s < (int)an.steps.size(); s++)
         if (!an.steps[s].dep) run_step(s);
+    // permuted copies of invariant operands of dependent steps: made once, kept
+    for (int s = 0; s < (int)an.steps.size(); s++) {
+        StepRec &st = an.steps[s];
+        if (st.hoist_a) {
+            scr_a[s] = ar.alloc(bytes_of(an.tensors[st.a]));
+            ar.release(off[st.a], bytes_of(an.tensors[st.a]));
+        }
+        if (st.hoist_b) {
+            scr_b[s] = ar.alloc(bytes_of(an.tensors[st.b]));
+            ar.release(off[st.b], bytes_of(an.tensors[st.b]));
+        }
+    }
     // dependent phase (one slice group)
     for (int i = 0; i < nT; i++)
         if (an.tensors[i].dep) off[i] = ar.alloc(bytes_of(an.tensors[i]));

@@ -28,6 +28,8 @@ struct StepRec {
     int64_t scr_a = -1, scr_b = -1;   // arena offsets of the permuted operands
     std::vector<int> a_from, b_from;  // operand orders before the permute
     int64_t M = 1, N = 1, K = 1, nb = 1;
+    int a_kc = 1, b_kc = 1, c_nc = 1;  // operand / result orientation (see GemmShape)
+    bool hoist_a = false, hoist_b = false;   // permute of an invariant operand, done once per call
     bool dep = false;
     int kernel = K_NAIVE;
     double flops = 0;                 // per slice (or once, if invariant)

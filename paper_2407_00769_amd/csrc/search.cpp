@@ -219,6 +219,194 @@ Sliced slice_tree(const Tree &t, int n_labels, const std::vector<char> &sliceabl
     return r;
 }
 
+
+// ------------------------------------------------------------------ subtree reconfiguration
+// For a node v, take the frontier of at most kMaxFront sub-trees below it and
+// find the cheapest way to contract them back into v by dynamic programming
+// over subsets (cost = per-slice flops, sliced labels removed; no
+// intermediate may exceed the cap).  Replace the old sub-tree when cheaper.
+
+constexpr int kMaxFront = 8;
+
+struct BTree {
+    int n = 0;                                  // inputs
+    std::vector<int> left, right;               // per node (-1 for inputs)
+    std::vector<std::vector<int>> labels;       // per node, sorted, sliced labels removed
+    int root = -1;
+};
+
+BTree to_btree(const Tree &t, int n_inputs, const std::vector<char> &sl) {
+    BTree b;
+    b.n = n_inputs;
+    const int total = (int)t.labels.size();
+    b.left.assign(total, -1);
+    b.right.assign(total, -1);
+    b.labels.resize(total);
+    for (int i = 0; i < total; i++)
+        for (int l : t.labels[i])
+            if (!sl[l]) b.labels[i].push_back(l);
+    for (size_t s = 0; s < t.ssa.size() / 2; s++) {
+        b.left[n_inputs + s] = t.ssa[2 * s];
+        b.right[n_inputs + s] = t.ssa[2 * s + 1];
+    }
+    b.root = total - 1;
+    return b;
+}
+
+double node_cost(const BTree &b, int v) {
+    if (b.left[v] < 0) return 0.0;
+    std::vector<int> u;
+    symdiff(b.labels[b.left[v]], b.labels[b.right[v]], &u);
+    return std::ldexp(8.0, (int)u.size());
+}
+
+double subtree_cost(const BTree &b, int v, const std::vector<char> &stop) {
+    if (b.left[v] < 0 || stop[v]) return 0.0;
+    return node_cost(b, v) + subtree_cost(b, b.left[v], stop) + subtree_cost(b, b.right[v], stop);
+}
+
+// returns the number of improved nodes
+int reconfigure_once(BTree &b, double cap, std::mt19937_64 &rng) {
+    int improved = 0;
+    const int total = (int)b.left.size();
+    std::vector<int> order;
+    for (int v = b.n; v < total; v++)
+        if (b.left[v] >= 0) order.push_back(v);
+    std::shuffle(order.begin(), order.end(), rng);
+    std::vector<char> stop(total, 0);
+    for (int v : order) {
+        if (b.left[v] < 0) continue;
+        // frontier: expand the largest internal frontier node until kMaxFront
+        std::vector<int> front = {b.left[v], b.right[v]};
+        std::vector<int> inner = {v};
+        while ((int)front.size() < kMaxFront) {
+            int best = -1;
+            size_t bsz = 0;
+            for (int i = 0; i < (int)front.size(); i++) {
+                int f = front[i];
+                if (b.left[f] >= 0 && (best < 0 || b.labels[f].size() > bsz)) {
+                    best = i;
+                    bsz = b.labels[f].size();
+                }
+            }
+            if (best < 0) break;
+            int f = front[best];
+            inner.push_back(f);
+            front[best] = b.left[f];
+            front.push_back(b.right[f]);
+        }
+        const int m = (int)front.size();
+        if (m < 3) continue;
+        for (int f : front) stop[f] = 1;
+        double old_cost = subtree_cost(b, v, stop);
+        for (int f : front) stop[f] = 0;
+        // local label bitsets
+        std::vector<int> loc;
+        for (int f : front) loc.insert(loc.end(), b.labels[f].begin(), b.labels[f].end());
+        std::sort(loc.begin(), loc.end());
+        loc.erase(std::unique(loc.begin(), loc.end()), loc.end());
+        const int nw = ((int)loc.size() + 63) / 64;
+        if (nw > 8) continue;
+        const int NS = 1 << m;
+        std::vector<uint64_t> bits((size_t)NS * nw, 0);
+        for (int i = 0; i < m; i++)
+            for (int l : b.labels[front[i]]) {
+                int j = (int)(std::lower_bound(loc.begin(), loc.end(), l) - loc.begin());
+                bits[(size_t)(1 << i) * nw + j / 64] |= 1ull << (j % 64);
+            }
+        std::vector<int> pc(NS, 0);
+        for (int S = 1; S < NS; S++) {
+            int low = S & -S;
+            if (S != low)
+                for (int w = 0; w < nw; w++) bits[(size_t)S * nw + w] = bits[(size_t)(S ^ low) * nw + w] ^ bits[(size_t)low * nw + w];
+            int c = 0;
+            for (int w = 0; w < nw; w++) c += __builtin_popcountll(bits[(size_t)S * nw + w]);
+            pc[S] = c;
+        }
+        std::vector<double> cost(NS, 1e300);
+        std::vector<int> split(NS, 0);
+        for (int i = 0; i < m; i++) cost[1 << i] = 0.0;
+        for (int S = 1; S < NS; S++) {
+            if ((S & (S - 1)) == 0) continue;
+            if (pc[S] > cap) continue;
+            // enumerate splits S1 containing the lowest bit of S
+            int low = S & -S;
+            for (int S1 = (S - 1) & S; S1 > 0; S1 = (S1 - 1) & S) {
+                if (!(S1 & low)) continue;
+                int S2 = S ^ S1;
+                if (cost[S1] >= 1e299 || cost[S2] >= 1e299) continue;
+                int uni = 0;
+                for (int w = 0; w < nw; w++)
+                    uni += __builtin_popcountll(bits[(size_t)S1 * nw + w] | bits[(size_t)S2 * nw + w]);
+                double c = cost[S1] + cost[S2] + std::ldexp(8.0, uni);
+                if (c < cost[S]) {
+                    cost[S] = c;
+                    split[S] = S1;
+                }
+            }
+        }
+        if (!(cost[NS - 1] < old_cost * (1.0 - 1e-9))) continue;
+        // rebuild: reuse the inner node ids (v keeps its id as the sub-tree root)
+        std::vector<int> pool(inner.begin() + 1, inner.end());
+        std::function<int(int, bool)> build = [&](int S, bool is_root) -> int {
+            if ((S & (S - 1)) == 0) return front[__builtin_ctz(S)];
+            int S1 = split[S], S2 = S ^ S1;
+            int a = build(S1, false), c2 = build(S2, false);
+            int id = is_root ? v : pool.back();
+            if (!is_root) pool.pop_back();
+            b.left[id] = a;
+            b.right[id] = c2;
+            std::vector<int> u;
+            b.labels[id] = symdiff(b.labels[a], b.labels[c2], &u);
+            return id;
+        };
+        build(NS - 1, true);
+        improved++;
+    }
+    return improved;
+}
+
+// post-order SSA path of a BTree (inputs keep their ids)
+std::vector<int> btree_ssa(const BTree &b) {
+    std::vector<int> ssa;
+    std::vector<int> newid(b.left.size(), -1);
+    for (int i = 0; i < b.n; i++) newid[i] = i;
+    int next = b.n;
+    std::vector<std::pair<int, int>> st = {{b.root, 0}};
+    while (!st.empty()) {
+        auto &[v, state] = st.back();
+        if (b.left[v] < 0) {
+            st.pop_back();
+            continue;
+        }
+        if (state == 0) {
+            state = 1;
+            int l = b.left[v], r = b.right[v];
+            st.push_back({r, 0});
+            st.push_back({l, 0});
+            continue;
+        }
+        ssa.push_back(newid[b.left[v]]);
+        ssa.push_back(newid[b.right[v]]);
+        newid[v] = next++;
+        st.pop_back();
+    }
+    return ssa;
+}
+
+Tree tree_from_ssa(const std::vector<std::vector<int>> &inputs, const std::vector<int> &ssa) {
+    Tree t;
+    t.labels = inputs;
+    t.labels.resize(inputs.size() * 2 - 1);
+    t.ssa = ssa;
+    std::vector<int> u;
+    for (size_t s = 0; s < ssa.size() / 2; s++) {
+        t.labels[inputs.size() + s] = symdiff(t.labels[ssa[2 * s]], t.labels[ssa[2 * s + 1]], &u);
+        t.uni.push_back(u);
+    }
+    return t;
+}
+
 }  // namespace
 
 extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_t *open_qubits, double log2_cap,
@@ -247,6 +435,8 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
         double best_cost = 1e300;
         std::vector<int> best_ssa, best_sl;
         double best_flops = 0;
+        const char *rc = getenv("TNC_SEARCH_RECONF");
+        const int reconf_rounds = rc ? atoi(rc) : 8;
         for (int r = 0; r < restarts; r++) {
             double alpha = r == 0 ? 1.0 : ua(rng);
             double temp = r == 0 ? 0.0 : ut(rng) * ut(rng);
@@ -280,6 +470,30 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
                 for (int l : s.labels) sl[l] = 1;
             }
             if (s.max_rank > log2_cap) continue;
+            // local improvement: reconfigure sub-trees under the cap with the sliced
+            // labels removed, then re-slice (the cap may now need fewer labels)
+            if (reconf_rounds > 0) {
+                auto inputs = reduced_inputs(net, gone);
+                for (int rr = 0; rr < 2; rr++) {
+                    std::vector<char> slv(L, 0);
+                    for (int l : s.labels) slv[l] = 1;
+                    BTree bt = to_btree(t, net.n_tensors, slv);
+                    for (int q = 0; q < reconf_rounds; q++)
+                        if (reconfigure_once(bt, log2_cap, rng) == 0) break;
+                    Tree t2 = tree_from_ssa(inputs, btree_ssa(bt));
+                    // drop sliced labels the new tree no longer needs, most expensive first
+                    std::vector<char> sl2(L, 0);
+                    Sliced s2 = slice_tree(t2, L, sliceable, log2_cap, sl2);
+                    Sliced s3 = slice_tree(t2, L, sliceable, log2_cap, slv);
+                    Sliced &pick = (s2.log2_total <= s3.log2_total) ? s2 : s3;
+                    if (pick.max_rank <= log2_cap && pick.log2_total < s.log2_total) {
+                        t = t2;
+                        s = pick;
+                    } else {
+                        break;
+                    }
+                }
+            }
             double cost = s.log2_total;
             if (cost_model == 1) {
                 double c = mlp_path_cost(net, t.ssa, s.labels, open_q);

@@ -1,0 +1,140 @@
+"""The learned step-cost model on the GPU.
+
+* Device gradients (the library's forward and backward kernels, FP32) match
+  the FP64 oracle's analytic gradients (themselves pinned by finite
+  differences) within 1e-4 relative.
+* Training is deterministic for a seed and reduces the loss.
+* Trained on the engine's own step timings, the MLP predicts held-out step
+  times better than the FLOP model with a fitted scale.
+* Steering the path search with it gives a path whose measured time is not
+  worse than the FLOP-steered path (the gain is printed).
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import workloads  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_00769_amd import _tnc
+    return _tnc
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    ws = torch.empty(16 << 30, dtype=torch.uint8, device="cuda:0")
+    c = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    yield c
+    T.tnc_destroy(c)
+    torch.cuda.synchronize()
+    del ws
+
+
+def _rows(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.column_stack([rng.integers(0, 17, n), rng.integers(0, 17, n), rng.integers(0, 17, n),
+                         rng.integers(0, 9, n), rng.integers(0, 3, n), rng.integers(0, 3, n),
+                         rng.integers(0, 3, n), rng.integers(0, 2, n)]).astype(np.float32)
+    y = (0.5 * x[:, 0] + 0.4 * x[:, 1] + 0.3 * x[:, 2] - 8 + 0.2 * x[:, 4]).astype(np.float32)
+    return x, y
+
+
+def test_device_gradients_match_fp64_oracle(T, ctx):
+    x, y = _rows(256, 1)
+    p = omlp.init(3).astype(np.float32)
+    p[omlp.SIZES[0]:omlp.SIZES[0] + omlp.H] = 0.1
+    assert T.tnc_mlp_param_count() == omlp.N_PARAMS
+    T.tnc_mlp_set_params(ctx, p)
+    loss, g = T.tnc_mlp_grad(ctx, x, y)
+    l64, g64 = omlp.loss_and_grad(p.astype(np.float64), x.astype(np.float64), y.astype(np.float64))
+    assert abs(loss - l64) <= 1e-5 * abs(l64)
+    off = 0
+    for s in omlp.SIZES:
+        a, b = g[off:off + s].astype(np.float64), g64[off:off + s]
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b) + 1e-7, (off, s)
+        off += s
+    # predictions equal the oracle's forward pass
+    pred = T.tnc_mlp_predict(ctx, x)
+    ref, _ = omlp.forward(p.astype(np.float64), x.astype(np.float64))
+    np.testing.assert_allclose(pred, ref, rtol=1e-5, atol=1e-4)
+
+
+def test_training_is_deterministic_and_learns(T, ctx):
+    x, y = _rows(2048, 2)
+    l1 = T.tnc_mlp_train(ctx, x, y, epochs=20, batch=128, lr=3e-3, seed=7)
+    p1 = T.tnc_mlp_get_params(ctx)
+    l2 = T.tnc_mlp_train(ctx, x, y, epochs=20, batch=128, lr=3e-3, seed=7)
+    p2 = T.tnc_mlp_get_params(ctx)
+    np.testing.assert_array_equal(p1, p2)
+    assert l1 == l2
+    assert l1 < 0.02 * float(np.var(y)), (l1, float(np.var(y)))
+
+
+def _timing_data(T, ctx):
+    from paper_2407_00769_amd import costmodel
+    circs = []
+    for (rows, cols, cyc, seed) in [(4, 4, 10, 101), (4, 5, 10, 102), (5, 5, 12, 103), (4, 6, 12, 104),
+                                    (5, 6, 10, 105), (3, 4, 8, 106), (5, 6, 14, 107)]:
+        sites, cp = workloads.rect_grid(rows, cols)
+        circs.append(workloads.random_circuit(sites, cp, cyc, seed))
+    return costmodel.collect(ctx, circs, ["c64", "f16_4m", "f16_3m", "bf16_4m"], caps=[14, 18, 22],
+                             open_counts=[4, 8], restarts=2, seed=1)
+
+
+def test_mlp_beats_flop_model_and_steers_search(T, ctx):
+    from paper_2407_00769_amd import circuit_network as cn
+    from paper_2407_00769_amd import costmodel
+    t0 = time.perf_counter()
+    X, y, fl = _timing_data(T, ctx)
+    t_collect = time.perf_counter() - t0
+    n = len(y)
+    assert n > 2000, n
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(n)
+    tr, te = perm[: int(0.8 * n)], perm[int(0.8 * n):]
+    t0 = time.perf_counter()
+    loss = T.tnc_mlp_train(ctx, X[tr], y[tr], epochs=60, batch=256, lr=2e-3, seed=7)
+    t_train = time.perf_counter() - t0
+    pred = T.tnc_mlp_predict(ctx, X[te])
+    c = costmodel.flop_model_fit(fl[tr], y[tr])
+    base = costmodel.flop_model_predict(fl[te], c)
+    err_mlp = float(np.median(np.abs(pred - y[te])))
+    err_flop = float(np.median(np.abs(base - y[te])))
+    print(f"\nrows {n} (collect {t_collect:.1f} s, train {t_train:.1f} s, loss {loss:.4f}); held-out median "
+          f"|log2 error|: MLP {err_mlp:.3f}, FLOP model {err_flop:.3f}")
+    assert err_mlp < err_flop
+    # steer the search for the 30-qubit circuit and time both choices
+    T.tnc_costmodel_use(ctx)
+    c30 = workloads.config_circuit(2)
+    st = workloads.tn_structure(c30)
+    r, l, d, o = cn.network_arrays(c30, st)
+    net = T.tnc_network_create(r, l, d, c30.n_qubits, o)
+    open_q = list(range(20, 30))
+    bits = workloads.prefix_bitstrings(30, open_q, 1024, 3)
+    times = {}
+    for model in (0, 1):
+        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 23, cost_model=model, restarts=32, seed=1)
+        plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
+        nsl = 1 << len(sl)
+        T.tnc_execute(plan, bits, 0, nsl)
+        best = 1e9
+        for _ in range(3):
+            _, rep = T.tnc_execute(plan, bits, 0, nsl)
+            best = min(best, rep["seconds"])
+        times[model] = best
+        T.tnc_plan_destroy(plan)
+    T.tnc_costmodel_use(None)
+    T.tnc_network_destroy(net)
+    gain = times[0] / times[1]
+    print(f"30-qubit block: FLOP-steered {times[0] * 1e3:.2f} ms, MLP-steered {times[1] * 1e3:.2f} ms, "
+          f"gain x{gain:.3f}")
+    assert times[1] <= 1.10 * times[0]

@@ -101,9 +101,11 @@ def _check_contract(T, ctx, prec, nb, m, n, k, seed, scale_log2=0):
     return got, ref
 
 
-KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5}
+KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5, "mfma_xl": 6,
+           "mfma_l2": 7}
 SHAPES = [  # nb, m, n, k  (log2)
     (0, 9, 6, 5), (1, 8, 5, 3), (0, 10, 4, 6), (2, 7, 7, 4), (0, 8, 0, 2), (0, 6, 3, 0), (0, 12, 5, 7),
+    (0, 9, 8, 6), (1, 8, 7, 5),
 ]
 
 
@@ -113,6 +115,46 @@ def test_contract_kernels(T, ctx, prec, kname, monkeypatch):
     monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
     for i, (nb, m, n, k) in enumerate(SHAPES):
         _check_contract(T, ctx, prec, nb, m, n, k, seed=100 + i)
+
+
+def _oriented_case(rng, m, n, k, a_kc, b_kc, c_nc):
+    ml = list(range(0, m))
+    nl = list(range(m, m + n))
+    kl = list(range(m + n, m + n + k))
+    rng.shuffle(kl)
+    al = ml + kl if a_kc else kl + ml
+    bl = nl + kl if b_kc else kl + nl
+    cl = ml + nl if c_nc else nl + ml
+    a = (rng.normal(size=2 ** len(al)) + 1j * rng.normal(size=2 ** len(al))) / np.sqrt(2 * 2 ** k)
+    b = (rng.normal(size=2 ** len(bl)) + 1j * rng.normal(size=2 ** len(bl))) / np.sqrt(2)
+    return al, bl, cl, a, b
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kname", ["skinny", "mfma_s", "mfma_l", "mfma_xl", "mfma_l2", "mfma_w"])
+def test_contract_orientations(T, ctx, prec, kname, monkeypatch):
+    # every combination of A [m][k] / [k][m], B [n][k] / [k][n], C [m][n] / [n][m]
+    # runs without a permute and matches the oracle
+    monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
+    rng = np.random.default_rng(11)
+    for a_kc in (1, 0):
+        for b_kc in (1, 0):
+            for c_nc in (1, 0):
+                al, bl, cl, a, b = _oriented_case(rng, 9, 8, 5, a_kc, b_kc, c_nc)
+                A, av = to_storage(a, prec)
+                B, bv = to_storage(b, prec)
+                C = empty_storage((2 ** len(cl),), prec)
+                times, _ = T.tnc_contract(ctx, prec, A, al, B, bl, C, cl)
+                assert times[0] < 0.05 and times[1] < 0.05 and times[3] < 0.05   # no permute ran (ms)
+                got = from_storage(C, prec).reshape((2,) * len(cl))
+                ref = pairwise.contract_pair(av.reshape((2,) * len(al)), al, bv.reshape((2,) * len(bl)), bl, cl)
+                mag = pairwise.contract_pair(np.abs(av).reshape((2,) * len(al)), al,
+                                             np.abs(bv).reshape((2,) * len(bl)), bl, cl)
+                bound = 4 * 32 * 2.0 ** -24 * np.abs(mag) + U[prec] * np.abs(ref) * 1.01 + 1e-30
+                if prec.endswith("3m"):
+                    bound = bound + 6 * U[prec] * np.abs(mag)
+                err = np.abs(got - ref)
+                assert np.all(err <= bound), (prec, kname, a_kc, b_kc, c_nc, float(np.max(err / bound)))
 
 
 @pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m", "f16_3m"])
@@ -242,3 +284,41 @@ def test_execute_rejects_bad_calls(T, ctx):
     assert e.value.code == -2
     T.tnc_destroy(c2)
     T.tnc_network_destroy(net)
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16_4m", "f16_3m", "bf16_4m"])
+def test_config2_full_block_matches_oracle(T, ctx, prec):
+    """The benchmark's own workload at full size (30 qubits, 256-slice block in
+    one launch, 1024 bitstrings) against the stored oracle amplitudes."""
+    gold = os.path.join(GOLD, "config2_amplitudes.npy")
+    ref = np.load(gold)
+    from paper_2407_00769_amd import circuit_network as cn
+    c = workloads.config_circuit(2)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    open_q = list(range(20, 30))
+    for seed in range(1, 20):
+        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 23, restarts=64, seed=seed)
+        if len(sl) == 8:
+            break
+    assert len(sl) == 8
+    bits = workloads.prefix_bitstrings(30, open_q, 1024, 3)
+    ws = torch.empty(16 << 30, dtype=torch.uint8, device="cuda:0")
+    big = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    plan = T.tnc_plan_create(big, net, ssa, sl, open_q, prec)
+    out, rep = T.tnc_execute(plan, bits, 0, 256)
+    assert rep["graph_launches"] == 1 and rep["slices"] == 256
+    f = metrics.fidelity(ref, out)
+    rl = metrics.rel_l2(out, ref)
+    if prec == "c64":
+        assert f >= 1 - 1e-8 and rl <= 1e-4, (f, rl)
+    elif prec.startswith("f16"):
+        assert f >= 0.999 and rl <= 0.05, (f, rl)
+    else:
+        assert f >= 0.99, (f, rl)
+    T.tnc_plan_destroy(plan)
+    T.tnc_destroy(big)
+    T.tnc_network_destroy(net)
+    del ws
+    torch.cuda.empty_cache()
