@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the sliced tensor-network amplitude path on one MI355X.
 
-One step = one tnc_execute over the whole slice block of the workload (every
-slice through every contraction step and the FP64 cross-slice sum), launched
-as one HIP graph, with the inputs resident on the device.
+A step is one tnc_execute over one batch of slices of a fixed sliced path
+(every slice of the batch through every contraction step, then the FP64
+cross-slice sum), launched as one HIP graph with the inputs resident on the
+device; consecutive steps take consecutive slice ranges.
 
-Workload (default): 30-qubit 5x6 grid random circuit, 14 cycles + final
-layer, fSim(pi/2, pi/6), ABCD couplers; 8 sliced labels (256 slices, the
-whole block); 1024 bitstrings sharing a 20-bit prefix (qubits 0-19) with
-qubits 20-29 open.  The primary form is FP16 storage with FP32-accumulated
-matrix-core GEMMs; complex64 runs the same path for the speedup.
+Workloads:
+  53q (default) -- one GPU's share of a 53-qubit, 20-cycle random circuit on
+     the 54-site diagonal grid (one site dead): the stored sliced path
+     (paper_2407_00769_amd/paths/config3.json, largest tensor of a slice
+     2^33 entries), 4096 correlated amplitudes (qubits 41-52 open), batches of
+     8 slices; the default 8 steps cover the 64-slice block [0, 64).
+  30q -- 5x6 grid, 14 cycles, 8 sliced labels; one step is the whole
+     256-slice block; 1024 bitstrings sharing a 20-bit prefix.
+The primary form is FP16 storage with FP32-accumulated matrix-core GEMMs
+(4M); FP16-3M and BF16-4M run the same path; complex64 runs it with extra
+sliced labels where one slice would not fit (53q), normalised per original
+slice.
 
-Prints one JSON line.  Extra keys: s_per_slice, forms (every precision run),
-fidelity against the oracle, roofline of the dominant kernel (HIP events in
-a timed pass), cpu_baseline (the FP64 state-vector oracle on a bounded
-sample of gates, scaled to the whole circuit).
+Prints one JSON line.  Extra keys: s_per_slice, forms, fidelity, roofline
+(dominant kernel family, HIP events around every launch of a step-timed
+pass), cpu_baseline (the oracle on the host, bounded sample).
 """
 from __future__ import annotations
 
@@ -29,160 +36,203 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f16": 2516.6, "bf16": 2516.6, "c64": 157.3}     # dense MFMA TFLOP/s (fp32 MFMA for c64)
+PEAK = {"f16": 2516.6, "bf16": 2516.6, "c64": 157.3}     # dense MFMA TFLOP/s (FP32 MFMA for complex64)
 HBM_GBS = 8000.0
 RIDGE = {k: v * 1e12 / (HBM_GBS * 1e9) for k, v in PEAK.items()}
+DKEY = {"c64": "c64", "f16_4m": "f16", "f16_3m": "f16", "bf16_4m": "bf16", "bf16_3m": "bf16"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def setup_workload(args, T, cn, workloads):
+def kernel_family(kid):
+    return {0: "gemm_naive", 1: "gemm_skinny", 2: "gemm_mfma_s", 3: "gemm_mfma_m", 4: "gemm_mfma_l",
+            5: "gemm_mfma_w", 6: "gemm_mfma_xl", 7: "gemm_mfma_l2"}.get(int(kid), f"gemm_{kid}")
+
+
+# ------------------------------------------------------------------ workloads
+
+def setup_53q(args, T, cn, workloads):
+    path = json.load(open(os.path.join(ROOT, "paper_2407_00769_amd", "paths", "config3.json")))
+    c = workloads.config_circuit(3)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    assert len(r) == path["n_tensors"], "stored path does not match the network"
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    open_q = path["open_qubits"]
+    bits = workloads.subspace_bitstrings(53, open_q, 5)
+    return dict(name="53q", circuit=c, net=net, open_q=open_q, ssa=np.array(path["ssa"], np.int32),
+                sliced=np.array(path["sliced"], np.int32), sliced_c64=np.array(path["sliced_c64"], np.int32),
+                bits=bits, per_step=8, steps_default=8, search_seconds=path["search"]["seconds"],
+                label="53-qubit, 20-cycle diagonal-grid random circuit (one GPU's share): 8-slice batches of the "
+                      "stored sliced path (largest slice tensor 2^33 entries), 4096 correlated amplitudes")
+
+
+def setup_30q(args, T, cn, workloads):
     c = workloads.config_circuit(2)
     st = workloads.tn_structure(c)
     r, l, d, o = cn.network_arrays(c, st)
     net = T.tnc_network_create(r, l, d, c.n_qubits, o)
     open_q = list(range(20, 30))
     t0 = time.perf_counter()
-    ssa = sl = None
     for seed in range(1, 20):
-        ssa, sl, cost = T.tnc_search(net, len(r), open_q, args.cap, restarts=args.restarts, seed=seed)
-        if len(sl) == args.sliced:
+        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 22, restarts=64, seed=seed)
+        if len(sl) == 8:
             break
     t_search = time.perf_counter() - t0
     bits = workloads.prefix_bitstrings(30, open_q, 1024, 3)
-    return c, st, net, open_q, ssa, sl, bits, t_search
+    return dict(name="30q", circuit=c, net=net, open_q=open_q, ssa=ssa, sliced=sl, sliced_c64=sl, bits=bits,
+                per_step=256, steps_default=10, search_seconds=t_search,
+                label="30-qubit 5x6 grid random circuit, 14 cycles, 256-slice block (8 sliced labels), "
+                      "1024 bitstrings with a 20-bit shared prefix")
 
 
-def kernel_family(kid):
-    return {0: "gemm_naive", 1: "gemm_skinny", 2: "gemm_mfma_64x16", 3: "gemm_mfma_128x32",
-            4: "gemm_mfma_128x64", 5: "gemm_mfma_256x16"}.get(int(kid), f"gemm_{kid}")
+# ------------------------------------------------------------------ runs
 
+def run_form(T, ctx, w, prec, sliced, per_step, steps, warmup, torch):
+    plan = T.tnc_plan_create(ctx, w["net"], w["ssa"], sliced, w["open_q"], prec)
+    info = T.tnc_plan_info(plan)
+    total = 1 << len(sliced)
+    out = np.zeros(len(w["bits"]), dtype=np.complex128)
 
-def run_form(T, ctx, net, ssa, sl, open_q, bits, prec, args, torch):
-    plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, prec)
-    pinfo = T.tnc_plan_info(plan)
-    n = 1 << len(sl)
-    out = np.zeros(len(bits), dtype=np.complex128)
-    for _ in range(args.warmup):
-        T.tnc_execute(plan, bits, 0, n, out)
+    def rng(k):
+        b = (k * per_step) % total
+        return b, min(b + per_step, total)
+
+    for k in range(warmup):
+        T.tnc_execute(plan, w["bits"], *rng(k), out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    flops = 0.0
+    slices = 0
     rep = None
-    for _ in range(args.steps):
-        _, rep = T.tnc_execute(plan, bits, 0, n, out)
+    for k in range(steps):
+        b, e = rng(k)
+        _, rep = T.tnc_execute(plan, w["bits"], b, e, out)
+        flops += rep["flops"]
+        slices += e - b
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    res = {"plan": plan, "out": out.copy(), "sec_per_block": dt, "flops": rep["flops"], "replays": rep["replays"],
-           "graph_launches": rep["graph_launches"], "device_sec": rep["seconds"], "info": pinfo, "slices": n}
-    return res
+    dt = time.perf_counter() - t0
+    return {"plan": plan, "info": info, "seconds": dt, "flops": flops, "slices": slices,
+            "replays": rep["replays"] if rep else 0}
 
 
-def timed_kernels(T, plan, bits, n, n_steps, dtype_key, reps=3):
+def timed_kernels(T, plan, bits, begin, end, dtype_key):
     """Per kernel family: launches, total ms, algorithmic flops and bytes, from
-    HIP events around every launch of a step-by-step execute."""
-    T.tnc_plan_set_timing(plan, True)
+    HIP events around every launch of one step-timed execute."""
+    n_steps = T.tnc_plan_info(plan)["n_steps"]
     steps = T.tnc_plan_steps(plan, n_steps)
-    S = T.tnc_plan_info(plan)["slices_in_flight"]
-    fam = {}
     es = 8 if dtype_key == "c64" else 4
-    for _ in range(reps):
-        T.tnc_execute(plan, bits, 0, n)
-        g, p, launches = T.tnc_plan_step_times(plan, n_steps)
-        for i in range(n_steps):
-            if launches[i] == 0:
-                continue
-            sl_per_launch = (n / launches[i]) if steps["dep"][i] else 1.0
-            k = kernel_family(steps["kernel"][i])
-            d = fam.setdefault(k, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
-            d["ms"] += g[i]
-            d["launches"] += int(launches[i])
-            d["flops"] += steps["flops"][i] * sl_per_launch * launches[i]
-            d["bytes"] += steps["bytes"][i] * sl_per_launch * launches[i]
-            if p[i] > 0:
-                m, nn, kk, b = steps["log2_mnkb"][i]
-                pa, pb = (int(v == 2) for v in steps["perm_ab"][i])
-                pbytes = 0.0
-                if pa:
-                    pbytes += 2.0 * es * 2.0 ** (b + m + kk)
-                if pb:
-                    pbytes += 2.0 * es * 2.0 ** (b + nn + kk)
-                d2 = fam.setdefault("permute", {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
-                d2["ms"] += p[i]
-                d2["launches"] += int(launches[i]) * (int(pa) + int(pb))
-                d2["bytes"] += pbytes * sl_per_launch * launches[i]
+    T.tnc_plan_set_timing(plan, True)
+    T.tnc_execute(plan, bits, begin, end)
+    g, p, launches = T.tnc_plan_step_times(plan, n_steps)
     T.tnc_plan_set_timing(plan, False)
-    for d in fam.values():
-        d["ms"] /= reps
-        d["launches"] //= reps
-        d["flops"] /= reps
-        d["bytes"] /= reps
+    n = end - begin
+    fam = {}
+    for i in range(n_steps):
+        if launches[i] == 0:
+            continue
+        per = (n / launches[i]) if steps["dep"][i] else 1.0
+        k = kernel_family(steps["kernel"][i])
+        d = fam.setdefault(k, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+        d["ms"] += g[i]
+        d["launches"] += int(launches[i])
+        d["flops"] += steps["flops"][i] * per * launches[i]
+        d["bytes"] += steps["bytes"][i] * per * launches[i]
+        if p[i] > 0:
+            m, nn, kk, b = steps["log2_mnkb"][i]
+            pa, pb = (int(v == 2) for v in steps["perm_ab"][i])
+            pbytes = (2.0 * es * 2.0 ** (b + m + kk) if pa else 0.0) + (2.0 * es * 2.0 ** (b + nn + kk) if pb else 0.0)
+            d2 = fam.setdefault("permute", {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+            d2["ms"] += p[i]
+            d2["launches"] += int(launches[i]) * (pa + pb)
+            d2["bytes"] += pbytes * per * launches[i]
     return fam
 
 
 def roofline_entry(fam, dtype_key):
     name, d = max(fam.items(), key=lambda kv: kv[1]["ms"])
     sec = d["ms"] * 1e-3
-    per_launch_ms = d["ms"] / max(1, d["launches"])
     if name == "permute":
         bound = "hbm"
     else:
-        inten = d["flops"] / max(d["bytes"], 1.0)
-        bound = "mfma" if inten >= RIDGE[dtype_key] else "hbm"
+        bound = "mfma" if d["flops"] / max(d["bytes"], 1.0) >= RIDGE[dtype_key] else "hbm"
     if bound == "mfma":
-        ach = d["flops"] / sec / 1e12
-        peak = PEAK[dtype_key]
-        unit = "TFLOP/s"
+        ach, peak, unit = d["flops"] / sec / 1e12, PEAK[dtype_key], "TFLOP/s"
     else:
-        ach = d["bytes"] / sec / 1e9
-        peak = HBM_GBS
-        unit = "GB/s"
+        ach, peak, unit = d["bytes"] / sec / 1e9, HBM_GBS, "GB/s"
+    total_ms = sum(v["ms"] for v in fam.values())
     return {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": None, "launches": d["launches"],
-            "avg_launch_us": round(per_launch_ms * 1e3, 3),
-            "share_of_device_time": round(d["ms"] / sum(v["ms"] for v in fam.values()), 4)}
+            "avg_launch_us": round(d["ms"] / max(1, d["launches"]) * 1e3, 3),
+            "share_of_device_time": round(d["ms"] / total_ms, 4),
+            "families": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                             "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 2)} for k, v in fam.items()}}
 
 
-def cpu_baseline(c, block_flops, n_slices, seconds_target):
-    """FP64 state-vector oracle on the host: time a bounded prefix of gates
-    and scale to the whole circuit."""
+# ------------------------------------------------------------------ CPU baselines (the oracle)
+
+def cpu_baseline_sv(c, block_flops, n_slices, seconds_target):
+    """FP64 state-vector oracle over a bounded prefix of the gates, scaled to
+    the whole circuit (it produces every amplitude of the block)."""
     from oracle import statevector
     threads = statevector.threads()
     n_g = len(c.gates)
     t0 = time.perf_counter()
     statevector.simulate(c, stop=2)
-    t_probe = time.perf_counter() - t0
-    per_gate_guess = max(t_probe / 2.0, 1e-3)
-    g = int(min(n_g, max(4, seconds_target / per_gate_guess)))
+    per_gate = max((time.perf_counter() - t0) / 2.0, 1e-3)
+    g = int(min(n_g, max(4, seconds_target / per_gate)))
     t0 = time.perf_counter()
     statevector.simulate(c, stop=g)
     t_s = time.perf_counter() - t0
     t_full = t_s * n_g / g
     return {"value": round(block_flops / t_full / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 state vector (2^{c.n_qubits} amplitudes) over the first {g} of {n_g} gates "
-                      f"in {t_s:.1f} s, scaled to all gates: {t_full:.1f} s per block of {n_slices} slices; "
-                      f"value = the block's algorithmic contraction flops / that time",
-            "seconds_per_block": round(t_full, 3)}
+            "sample": f"FP64 state vector (2^{c.n_qubits} amplitudes) over the first {g} of {n_g} gates in "
+                      f"{t_s:.1f} s, scaled to all gates: {t_full:.1f} s for the {n_slices}-slice block; value = "
+                      f"the block's algorithmic contraction flops / that time",
+            "seconds_per_slice": t_full / n_slices}
+
+
+def cpu_baseline_einsum(flops_per_slice, seconds_target):
+    """FP64 pairwise contraction of the oracle (numpy complex128 einsum) timed
+    on a representative step shape; the per-slice time is an estimate."""
+    from oracle import pairwise
+    rng = np.random.default_rng(0)
+    # a stem-like step: C has 2^13 x 2^9 entries, 2^10 reduced (3.4e10 flops)
+    la, lb, lc = list(range(0, 23)), list(range(13, 32)), list(range(0, 13)) + list(range(23, 32))
+    a = rng.normal(size=(2,) * 23) + 1j * rng.normal(size=(2,) * 23)
+    b = rng.normal(size=(2,) * 19) + 1j * rng.normal(size=(2,) * 19)
+    fl = 8.0 * 2 ** 32
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < seconds_target:
+        pairwise.contract_pair(a, la, b, lb, lc)
+        reps += 1
+    dt = time.perf_counter() - t0
+    rate = fl * reps / dt
+    return {"value": round(rate / 1e12, 6), "unit": "TFLOP/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"oracle pairwise contraction (numpy complex128 einsum) of a 2^13 x 2^9 x 2^10 step, "
+                      f"{reps} runs in {dt:.1f} s = {rate / 1e9:.1f} GFLOP/s; estimated "
+                      f"{flops_per_slice / rate:.0f} s per slice (no full oracle exists for 53 qubits)",
+            "seconds_per_slice": flops_per_slice / rate}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="53q", choices=["53q", "30q"])
     ap.add_argument("--prec", default="f16_4m")
     ap.add_argument("--compare", default="c64,f16_3m,bf16_4m")
-    ap.add_argument("--cap", type=float, default=23)
-    ap.add_argument("--sliced", type=int, default=8)
-    ap.add_argument("--restarts", type=int, default=64)
-    ap.add_argument("--workspace-gb", type=float, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the slice blocks of several GPUs "
-              f"would be independent and are not launched here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): slice blocks on several GPUs "
+              f"would be independent ranges summed by one all-reduce, which this build does not launch",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -192,83 +242,114 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     dev = torch.device("cuda:0")
-    c, st, net, open_q, ssa, sl, bits, t_search = setup_workload(args, T, cn, workloads)
-    log(f"search: {len(sl)} sliced labels, {t_search:.2f} s")
-    ws = torch.empty(int(args.workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.Stream()
-    ctx = T.tnc_create(0, ws, stream=stream)
+    w = (setup_53q if args.workload == "53q" else setup_30q)(args, T, cn, workloads)
+    steps = args.steps if args.steps is not None else w["steps_default"]
+    free, _total = torch.cuda.mem_get_info()
+    ws_bytes = int(min(free - (12 << 30), 200 << 30))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    log(f"workload {w['name']}: {len(w['sliced'])} sliced labels, workspace {ws_bytes / 2**30:.0f} GiB")
+
     forms = [args.prec] + [p for p in args.compare.split(",") if p and p != args.prec]
-    results = {}
+    res = {}
     for prec in forms:
-        results[prec] = run_form(T, ctx, net, ssa, sl, open_q, bits, prec, args, torch)
-        r = results[prec]
-        log(f"{prec}: {r['sec_per_block'] * 1e3:.2f} ms/block, {r['flops'] / r['sec_per_block'] / 1e12:.2f} TFLOP/s")
+        if prec == "c64" and w["name"] == "53q":
+            # complex64 runs the path with extra sliced labels; time 4 of its slices
+            extra = len(w["sliced_c64"]) - len(w["sliced"])
+            r = run_form(T, ctx, w, prec, w["sliced_c64"], 4, 1, 1, torch)
+            r["per_original_slice"] = r["seconds"] / r["slices"] * (1 << extra)
+        else:
+            r = run_form(T, ctx, w, prec, w["sliced"], w["per_step"], steps if prec == args.prec else 1,
+                         args.warmup if prec == args.prec else 1, torch)
+            r["per_original_slice"] = r["seconds"] / r["slices"]
+        res[prec] = r
+        log(f"{prec}: {r['seconds'] / r['slices'] * 1e3:.2f} ms per slice run, "
+            f"{r['flops'] / r['seconds'] / 1e12:.2f} TFLOP/s, tune {r['info']['tune_seconds']:.1f} s")
+    main_r = res[args.prec]
 
-    gold_path = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.npy")
-    ref = np.load(gold_path) if os.path.exists(gold_path) else None
-    ref_kind = "oracle (FP64 state vector)" if ref is not None else "complex64 GPU run"
-    if ref is None:
-        ref = results["c64"]["out"] if "c64" in results else None
+    # fidelity: the stored oracle amplitudes (30q) or the complex64 run of slice 0 (53q)
+    bits = w["bits"]
+    ref, ref_kind = None, None
+    if w["name"] == "30q":
+        gold = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.npy")
+        if os.path.exists(gold):
+            ref = np.load(gold)
+            ref_kind = "oracle (FP64 state vector, stored)"
+    if ref is None and "c64" in res:
+        if w["name"] == "53q":
+            extra = len(w["sliced_c64"]) - len(w["sliced"])
+            ref = np.zeros(len(bits), complex)
+            for j in range(1 << extra):
+                lo = j << len(w["sliced"])
+                o, _ = T.tnc_execute(res["c64"]["plan"], bits, lo, lo + 1)
+                ref += o
+            ref_kind = "complex64 GPU run of slice 0 (the sum of its 4 complex64 sub-slices); no full oracle for 53 qubits"
+        else:
+            ref, _ = T.tnc_execute(res["c64"]["plan"], bits, 0, main_r["slices"])
+            ref_kind = "complex64 GPU run"
 
-    def fid(out):
-        if ref is None:
-            return None
+    def fid(prec):
+        if ref is None or (prec == "c64" and w["name"] == "53q"):
+            return None, None
+        n = 1 if w["name"] == "53q" else 1 << len(w["sliced"])
+        o, _ = T.tnc_execute(res[prec]["plan"], bits, 0, n)
         b = ref.ravel()
-        r = out.ravel()
-        f = abs(np.vdot(b, r)) ** 2 / (np.vdot(b, b).real * np.vdot(r, r).real)
-        return float(f), float(np.linalg.norm(r - b) / np.linalg.norm(b))
-
-    main_r = results[args.prec]
-    n = main_r["slices"]
-    dkey = "c64" if args.prec == "c64" else args.prec.split("_")[0]
-    fam = timed_kernels(T, main_r["plan"], bits, n, len(ssa) // 2, dkey)
-    roof = roofline_entry(fam, dkey)
+        f = abs(np.vdot(b, o)) ** 2 / (np.vdot(b, b).real * np.vdot(o, o).real)
+        return float(f), float(np.linalg.norm(o - b) / np.linalg.norm(b))
 
     forms_out = {}
-    for prec, r in results.items():
-        f = fid(r["out"])
-        forms_out[prec] = {"tflops": round(r["flops"] / r["sec_per_block"] / 1e12, 3),
-                           "s_per_slice": r["sec_per_block"] / n,
-                           "ms_per_block": round(r["sec_per_block"] * 1e3, 3),
-                           "fidelity": None if f is None else round(f[0], 9),
-                           "rel_l2": None if f is None else f[1], "replays": r["replays"]}
-    if "c64" in results and args.prec != "c64":
-        forms_out[args.prec]["speedup_vs_c64"] = round(results["c64"]["sec_per_block"] / main_r["sec_per_block"], 3)
+    for prec, r in res.items():
+        f, rl = fid(prec)
+        forms_out[prec] = {"tflops": round(r["flops"] / r["seconds"] / 1e12, 3),
+                           "s_per_slice": r["per_original_slice"], "slices_timed": r["slices"],
+                           "fidelity": None if f is None else round(f, 9), "rel_l2": rl, "replays": r["replays"],
+                           "slices_in_flight": r["info"]["slices_in_flight"],
+                           "tune_seconds": round(r["info"]["tune_seconds"], 2)}
+    if "c64" in res and args.prec != "c64":
+        forms_out[args.prec]["speedup_vs_c64"] = round(res["c64"]["per_original_slice"] / main_r["per_original_slice"], 3)
+
+    dkey = DKEY[args.prec]
+    fam = timed_kernels(T, main_r["plan"], bits, 0, min(w["per_step"], 1 << len(w["sliced"])), dkey)
+    roof = roofline_entry(fam, dkey)
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(c, main_r["flops"], n, args.cpu_seconds)
+        if w["name"] == "30q":
+            cpu = cpu_baseline_sv(w["circuit"], main_r["flops"] / steps, main_r["slices"] // steps, args.cpu_seconds)
+        else:
+            cpu = cpu_baseline_einsum(main_r["info"]["flops_per_slice"], args.cpu_seconds)
 
-    value = main_r["flops"] / main_r["sec_per_block"] / 1e12
+    value = main_r["flops"] / main_r["seconds"] / 1e12
     line = {
         "metric": "complex-contraction TFLOPS + s/slice, fp16-MFMA vs c64, at stated fidelity",
         "value": round(value, 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(main_r["sec_per_block"] * 1e3, 3),
+        "ms_per_step": round(main_r["seconds"] / steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f16_4m": "f16", "f16_3m": "f16", "bf16_4m": "bf16", "bf16_3m": "bf16", "c64": "f32"}[args.prec],
         "data": "synthetic",
-        "config": {"workload": "30-qubit 5x6 grid random circuit, 14 cycles, 256-slice block (8 sliced labels), "
-                               "1024 bitstrings with a 20-bit shared prefix",
-                   "precision": args.prec, "slices": n, "bitstrings": int(len(bits)),
+        "config": {"workload": w["label"], "precision": args.prec, "slices_per_step": w["per_step"],
+                   "slices_timed": main_r["slices"], "bitstrings": int(len(bits)),
+                   "sliced_labels": int(len(w["sliced"])),
                    "slices_in_flight": main_r["info"]["slices_in_flight"],
-                   "flops_per_block": main_r["flops"], "max_rank": main_r["info"]["max_rank"],
-                   "search_seconds": round(t_search, 3)},
-        "s_per_slice": main_r["sec_per_block"] / n,
+                   "flops_per_slice": main_r["info"]["flops_per_slice"],
+                   "peak_bytes": main_r["info"]["peak_bytes"], "max_rank": main_r["info"]["max_rank"],
+                   "search_seconds": round(w["search_seconds"], 2)},
+        "s_per_slice": main_r["seconds"] / main_r["slices"],
         "fidelity": forms_out[args.prec]["fidelity"],
         "fidelity_reference": ref_kind,
         "forms": forms_out,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    for r in results.values():
+    for r in res.values():
         T.tnc_plan_destroy(r["plan"])
-    T.tnc_network_destroy(net)
+    T.tnc_network_destroy(w["net"])
     T.tnc_destroy(ctx)
     print(json.dumps(line), flush=True)
 

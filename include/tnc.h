@@ -146,6 +146,14 @@ int tnc_search(const tnc_network *net, int32_t n_open, const int32_t *open_qubit
                int32_t cost_model, int32_t restarts, uint64_t seed, int32_t *ssa_out,
                int32_t max_sliced, int32_t *sliced_out, int32_t *n_sliced, double *log2_cost_out);
 
+/* Slice an existing path further: starting from sliced_in[n_in], add sliced
+ * labels (cheapest added work first) until no tensor of one slice exceeds
+ * 2^log2_cap entries.  sliced_out (host, capacity max_sliced) receives the
+ * whole set, the given labels first, in order; n_out the count. */
+int tnc_slice_path(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs, int32_t n_open,
+                   const int32_t *open_qubits, double log2_cap, int32_t n_in, const int32_t *sliced_in,
+                   int32_t max_sliced, int32_t *sliced_out, int32_t *n_out);
+
 /* ------------------------------------------------------------------ plan */
 
 /* Compile a path for execution on ctx's device.  Every step's GEMM kernel

@@ -151,3 +151,41 @@ def brute_force(tensors, output_labels, fixed=None):
             acc += p
         res[ov] = acc
     return res
+
+
+def contract_path(tensors, output_labels, ssa, fixed=None):
+    """Contract along a given pairwise order (SSA pairs: ids >= len(tensors)
+    name earlier results).  The network's value does not depend on the order
+    in exact arithmetic, so the order only changes FP64 rounding; it is data
+    here, not arithmetic.  A label is summed when no other live tensor and no
+    output holds it."""
+    ts = fix_labels(tensors, fixed or {})
+    out = tuple(l for l in output_labels if not (fixed and l in fixed))
+    outset = set(out)
+    live = {i: t for i, t in enumerate(ts)}
+    count = {}
+    for labels, _d in ts:
+        for l in labels:
+            count[l] = count.get(l, 0) + 1
+    nxt = len(ts)
+    for s in range(len(ssa) // 2):
+        i, j = int(ssa[2 * s]), int(ssa[2 * s + 1])
+        la, lb = live[i][0], live[j][0]
+        keep = set()
+        for l in set(la) | set(lb):
+            others = count[l] - (l in la) - (l in lb)
+            if l in outset or others > 0:
+                keep.add(l)
+        lc, dc = _pair(live[i], live[j], keep)
+        for l in set(la) | set(lb):
+            count[l] -= (l in la) + (l in lb)
+        for l in lc:
+            count[l] = count.get(l, 0) + 1
+        del live[i]
+        del live[j]
+        live[nxt] = (lc, dc)
+        nxt += 1
+    (labels, data), = live.values()
+    if set(labels) != set(out):
+        raise ValueError("path does not reduce to the output labels")
+    return np.transpose(data, [labels.index(l) for l in out]) if out else data

@@ -65,6 +65,8 @@ _SIGS = {
     "tnc_network_destroy": (ctypes.c_int, [vp]),
     "tnc_search": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_uint64, c_int32_p, ctypes.c_int32, c_int32_p, c_int32_p, c_double_p]),
+    "tnc_slice_path": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p, ctypes.c_double,
+                                      ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p, c_int32_p]),
     "tnc_plan_create": (ctypes.c_int, [vp, vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
                                        ctypes.c_int32, c_int32_p, ctypes.c_int, ctypes.c_int32,
                                        ctypes.POINTER(vp)]),
@@ -177,6 +179,17 @@ def tnc_search(net, n_tensors, open_qubits, log2_cap, cost_model=0, restarts=8, 
                           ssa.ctypes.data_as(c_int32_p), int(max_sliced), sl.ctypes.data_as(c_int32_p),
                           ctypes.byref(ns), ctypes.byref(cost)))
     return ssa, sl[:ns.value].copy(), cost.value
+
+
+def tnc_slice_path(net, ssa, open_qubits, log2_cap, sliced_in=(), max_sliced=62):
+    s, sp = _i32(ssa)
+    oq, op = _i32(open_qubits)
+    si, sip = _i32(list(sliced_in))
+    out = np.zeros(max_sliced, dtype=np.int32)
+    n = ctypes.c_int32(0)
+    _check(lib.tnc_slice_path(net, len(s) // 2, sp, len(oq), op, float(log2_cap), len(si), sip, int(max_sliced),
+                              out.ctypes.data_as(c_int32_p), ctypes.byref(n)))
+    return out[:n.value].copy()
 
 
 def tnc_plan_create(ctx, net, ssa, sliced, open_qubits, precision, max_slices_in_flight=0):

@@ -144,6 +144,29 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
         if ((size_t)off > ctx->ws_bytes) TNC_THROW(TNC_ENOMEM, "workspace too small for the permuted operands");
         HIP_CHECK(hipSetDevice(ctx->device));
         hipStream_t st = ctx->stream;
+        // scale bookkeeping in the context's small buffer: maxA = maxB = 1.0,
+        // so shift = growth - target = scale_log2
+        uint8_t *sm = ctx->small;
+        ScaleRefs sc{};
+        if (dt != Dtype::C64) {
+            struct Small {
+                uint32_t maxA, maxB, maxC, flag;
+                int growth, shift, pad0, pad1;
+                double expA, expB, expC;
+            } h{0x3f800000u, 0x3f800000u, 0u, 0u, scale_log2 + 13, 0, 0, 0, 0.0, 0.0, 0.0};
+            HIP_CHECK(hipMemcpyAsync(sm, &h, sizeof(h), hipMemcpyHostToDevice, st));
+            HIP_CHECK(hipStreamSynchronize(st));   // h lives on this stack frame
+            Small *d = (Small *)sm;
+            sc.maxA = &d->maxA;
+            sc.maxB = &d->maxB;
+            sc.maxC = &d->maxC;
+            sc.flag = &d->flag;
+            sc.growth = &d->growth;
+            sc.shift = &d->shift;
+            sc.expA = &d->expA;
+            sc.expB = &d->expB;
+            sc.expC = &d->expC;
+        }
         hipEvent_t ev[5];
         for (auto &e : ev) HIP_CHECK(hipEventCreate(&e));
         HIP_CHECK(hipEventRecord(ev[0], st));
@@ -170,31 +193,6 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
         g.b_kc = q_kc;
         g.c_nc = c_nc;
         void *pc = perm_c ? (void *)(ctx->ws + off_c) : C;
-        // scale bookkeeping in the context's small buffer: maxA = maxB = 1.0,
-        // so shift = growth - target = scale_log2
-        uint8_t *sm = ctx->small;
-        ScaleRefs sc{};
-        if (dt != Dtype::C64) {
-            struct Small {
-                uint32_t maxA, maxB, maxC, flag;
-                int growth, shift, pad0, pad1;
-                double expA, expB, expC;
-            } h{0x3f800000u, 0x3f800000u, 0u, 0u, scale_log2 + 13, 0, 0, 0, 0.0, 0.0, 0.0};
-            HIP_CHECK(hipMemcpyAsync(sm, &h, sizeof(h), hipMemcpyHostToDevice, st));
-            HIP_CHECK(hipStreamSynchronize(st));   // h lives on this stack frame
-            Small *d = (Small *)sm;
-            sc.maxA = &d->maxA;
-            sc.maxB = &d->maxB;
-            sc.maxC = &d->maxC;
-            sc.flag = &d->flag;
-            sc.growth = &d->growth;
-            sc.shift = &d->shift;
-            sc.expA = &d->expA;
-            sc.expB = &d->expB;
-            sc.expC = &d->expC;
-            // the 16-byte copy above is ordered before the GEMM on the same stream
-            HIP_CHECK(hipEventRecord(ev[2], st));
-        }
         int kid = choose_kernel(dt, al, g);
         const char *force = getenv("TNC_FORCE_KERNEL");
         if (force) {

@@ -365,8 +365,16 @@ double autotune_plan(tnc_plan *p) {
         g.c_nc = rec.c_nc;
         const int Sl = rec.dep ? p->S : 1;
         std::vector<int> cands;
-        for (int k = 1; k < K_COUNT; k++)
-            if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
+        // big steps: only the large matrix-core tiles are worth timing
+        const bool big = rec.flops * (double)Sl > 1e13;
+        static const int big_order[] = {K_MFMA_XL, K_MFMA_L2, K_MFMA_L};
+        if (big) {
+            for (int k : big_order)
+                if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
+        }
+        if (cands.empty())
+            for (int k = 1; k < K_COUNT; k++)
+                if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
         if (cands.size() <= 1) continue;
         TuneKey key((int)dt, (int)an.al, ilog2(g.M), ilog2(g.N), ilog2(g.K), ilog2(g.nb), g.a_kc, g.b_kc, g.c_nc);
         auto it = g_tune.find(key);
@@ -382,11 +390,13 @@ double autotune_plan(tnc_plan *p) {
         for (int k : cands) {
             launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);   // warm
             HIP_CHECK(hipEventRecord(e0, st));
-            for (int r = 0; r < 2; r++) launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+            const int reps = big ? 1 : 2;
+            for (int r = 0; r < reps; r++) launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
             HIP_CHECK(hipEventRecord(e1, st));
             HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0;
             HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            ms /= reps;
             if (ms < best) {
                 best = ms;
                 best_k = k;

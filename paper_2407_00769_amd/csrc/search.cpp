@@ -521,3 +521,47 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
         return TNC_EINVAL;
     }
 }
+
+extern "C" int tnc_slice_path(const tnc_network *net_h, int32_t n_steps, const int32_t *ssa_pairs, int32_t n_open,
+                              const int32_t *open_qubits, double log2_cap, int32_t n_in, const int32_t *sliced_in,
+                              int32_t max_sliced, int32_t *sliced_out, int32_t *n_out) {
+    try {
+        if (!net_h || !ssa_pairs || !sliced_out || !n_out || (n_in > 0 && !sliced_in)) TNC_THROW(TNC_EINVAL, "NULL argument");
+        const Network &net = net_h->net;
+        if (n_steps != net.n_tensors - 1) TNC_THROW(TNC_EINVAL, "path must have n_tensors - 1 steps");
+        const int L = net.n_labels;
+        std::vector<char> gone(L, 0), sliceable(L, 1), is_open(net.n_qubits, 0);
+        for (int i = 0; i < n_open; i++) {
+            int q = open_qubits[i];
+            if (q < 0 || q >= net.n_qubits || is_open[q]) TNC_THROW(TNC_EINVAL, "bad open qubit list");
+            is_open[q] = 1;
+        }
+        for (int q = 0; q < net.n_qubits; q++) {
+            sliceable[net.output_labels[q]] = 0;
+            if (!is_open[q]) gone[net.output_labels[q]] = 1;
+        }
+        std::vector<int> ssa(ssa_pairs, ssa_pairs + 2 * n_steps);
+        Tree t = tree_from_ssa(reduced_inputs(net, gone), ssa);
+        std::vector<char> sl(L, 0);
+        for (int j = 0; j < n_in; j++) {
+            int l = sliced_in[j];
+            if (l < 0 || l >= L || !sliceable[l]) TNC_THROW(TNC_EINVAL, "bad sliced label");
+            sl[l] = 1;
+        }
+        Sliced s = slice_tree(t, L, sliceable, log2_cap, sl);
+        if (s.max_rank > log2_cap) TNC_THROW(TNC_EINVAL, "the cap cannot be met by slicing");
+        std::vector<int> out(sliced_in, sliced_in + n_in);
+        for (int l : s.labels)
+            if (std::find(out.begin(), out.end(), l) == out.end()) out.push_back(l);
+        if ((int)out.size() > max_sliced) TNC_THROW(TNC_EINVAL, "more sliced labels than max_sliced");
+        std::copy(out.begin(), out.end(), sliced_out);
+        *n_out = (int)out.size();
+        return TNC_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return TNC_EINVAL;
+    }
+}

@@ -122,7 +122,7 @@ def test_mlp_beats_flop_model_and_steers_search(T, ctx):
     bits = workloads.prefix_bitstrings(30, open_q, 1024, 3)
     times = {}
     for model in (0, 1):
-        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 23, cost_model=model, restarts=32, seed=1)
+        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 22, cost_model=model, restarts=32, seed=1)
         plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
         nsl = 1 << len(sl)
         T.tnc_execute(plan, bits, 0, nsl)

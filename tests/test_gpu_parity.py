@@ -299,7 +299,7 @@ def test_config2_full_block_matches_oracle(T, ctx, prec):
     net = T.tnc_network_create(r, l, d, c.n_qubits, o)
     open_q = list(range(20, 30))
     for seed in range(1, 20):
-        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 23, restarts=64, seed=seed)
+        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 22, restarts=64, seed=seed)
         if len(sl) == 8:
             break
     assert len(sl) == 8

@@ -182,3 +182,28 @@ def test_porter_thomas_and_xeb_of_ideal_amplitudes():
     c0 = workloads.Circuit(4, [workloads.Gate("sqrtX", (q,)) for q in range(4)], [(0, q) for q in range(4)], 0, "A")
     p0 = np.abs(statevector.simulate(c0)) ** 2
     assert metrics.porter_thomas_ks(p0, 4) > 0.2
+
+
+def test_contract_path_equals_own_order_and_statevector():
+    c = _tiny(2, 3, 5, 13)
+    st = workloads.tn_structure(c)
+    ts = einsum.network_tensors(c, st)
+    ref = einsum.contract(ts, st.output_labels)
+    rng = np.random.default_rng(0)
+    for trial in range(4):
+        # a random order of merges along shared labels
+        labels = {i: set(t[0]) for i, t in enumerate(ts)}
+        ssa = []
+        nxt = len(ts)
+        while len(labels) > 1:
+            pairs = [(i, j) for i in labels for j in labels if i < j and labels[i] & labels[j]]
+            if not pairs:
+                pairs = [tuple(sorted(labels))[:2]]
+            i, j = pairs[rng.integers(len(pairs))]
+            labels[nxt] = labels.pop(i) ^ labels.pop(j)
+            ssa += [i, j]
+            nxt += 1
+        got = einsum.contract_path(ts, st.output_labels, ssa)
+        np.testing.assert_allclose(got, ref, atol=1e-12)
+    psi = statevector.simulate(c)
+    np.testing.assert_allclose(ref.reshape(-1), psi, atol=1e-12)
