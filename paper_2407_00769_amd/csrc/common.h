@@ -76,6 +76,11 @@ struct GemmShape {
     int64_t sA, sB, sC;         // slice strides (0 = shared by every slice)
     int64_t bA, bB, bC;         // inner-batch strides
     int a_kc = 1, b_kc = 1, c_nc = 1, pad_ = 0;
+    // split-K: the reduced range is cut into `split` parts; each part's FP32
+    // partial result goes to part[((s * nb + b) * split + p)][m][n] (re, im
+    // pairs) and a second kernel sums the parts in order
+    int64_t split = 1;
+    float2 *part = nullptr;
 };
 
 // Scale bookkeeping of the 16-bit forms, per tensor and slice.
@@ -113,6 +118,10 @@ void launch_permute(Dtype dt, const void *src, void *dst, const PermuteDesc &d, 
                     int S, int64_t src_slice_stride, const int64_t *d_slice_offsets,
                     int64_t dst_slice_stride, hipStream_t st);
 bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g);
+// split-K factor the launch of kernel kid would use for S slices (1 = none),
+// and the partial-result bytes it needs
+int64_t splitk_factor(int kid, Dtype dt, Algo al, const GemmShape &g, int S);
+int64_t splitk_bytes(int kid, Dtype dt, Algo al, const GemmShape &g, int S);
 void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void *C,
                  const GemmShape &g, int S, const ScaleRefs *sc, hipStream_t st);
 void launch_convert_c128(const double *src, int64_t n, Dtype dt, void *dst, hipStream_t st);
@@ -124,14 +133,22 @@ void launch_accumulate(Dtype dt, const void *R, int rank, int S, int64_t slice_s
                        const double *expR, int n_exp_stride, int64_t nbits, const uint64_t *d_bits,
                        const int *d_qubit_of_bit, double *acc, hipStream_t st);
 
-// Bits of an LDS-tiled permute: destination bits hi[i] hold source bits i
-// (i < w); rest lists the destination bits outside both w-bit sets.
+// Bits of an LDS-tiled permute.  The tile is the union T of the w lowest
+// destination bits and the destination bits that hold the w lowest source
+// bits, grown to nt_max bits (or the whole rank) with further low destination
+// and source bits in turn; src_order lists T's destination bits by source position, dst_order by
+// destination position, lds_bit[i] is the position of src_order[i] in
+// dst_order; rest lists the destination bits outside T.
 struct TileBits {
-    int hi[8];
+    int nt;
+    int src_order[16];
+    int dst_order[16];
+    int lds_bit[16];
     int rest[kMaxRank];
     int n_rest;
 };
-bool plan_tile_bits(const PermuteDesc &d, int lw, TileBits &tb);
+bool plan_tile_bits(const PermuteDesc &d, int lw, int nt_max, TileBits &tb);
+constexpr int kPermTileBits = 12;   // 4096 entries per LDS tile
 
 // Slice selection of one input tensor (see gather_leaves_kernel).
 constexpr int kMaxLeafRank = 16;

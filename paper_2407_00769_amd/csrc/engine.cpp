@@ -154,7 +154,7 @@ static void free_plan_device(tnc_plan *p) {
     for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
     p->graphs.clear();
     void *ptrs[] = {p->d_leafdata, p->d_desc, p->d_maxw, p->d_expw, p->d_shift, p->d_growth,
-                    p->d_flags,    p->d_params, p->d_bits, p->d_acc, p->d_qob};
+                    p->d_flags,    p->d_params, p->d_bits, p->d_acc, p->d_qob, p->d_part};
     for (void *q : ptrs)
         if (q) hipFree(q);
 }
@@ -274,6 +274,19 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
     p->d_qob = dev_alloc<int>((int64_t)qob.size());
     HIP_CHECK(hipMemcpyAsync(p->d_qob, qob.data(), sizeof(int) * qob.size(), hipMemcpyHostToDevice, st));
     HIP_CHECK(hipStreamSynchronize(st));
+    // split-K partial sums: the largest need of any step under any kernel variant
+    int64_t part_bytes = 0;
+    for (const auto &rec : an.steps) {
+        const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
+        GemmShape g{rec.M, rec.N, rec.K, rec.nb, A.dep ? 1 : 0, B.dep ? 1 : 0, 1, 0, 0, 0};
+        g.a_kc = rec.a_kc;
+        g.b_kc = rec.b_kc;
+        g.c_nc = rec.c_nc;
+        (void)Z;
+        for (int k = K_MFMA_S; k < K_COUNT; k++)
+            part_bytes = std::max(part_bytes, splitk_bytes(k, dt, an.al, g, rec.dep ? S : 1));
+    }
+    if (part_bytes > 0) p->d_part = (float2 *)dev_alloc<uint8_t>(part_bytes);
     p->step_ms.assign(ns, 0.0);
     p->perm_ms.assign(ns, 0.0);
     p->step_launches.assign(ns, 0);
@@ -363,6 +376,7 @@ double autotune_plan(tnc_plan *p) {
         g.a_kc = rec.a_kc;
         g.b_kc = rec.b_kc;
         g.c_nc = rec.c_nc;
+        g.part = p->d_part;
         const int Sl = rec.dep ? p->S : 1;
         std::vector<int> cands;
         // big steps: only the large matrix-core tiles are worth timing
@@ -372,9 +386,13 @@ double autotune_plan(tnc_plan *p) {
             for (int k : big_order)
                 if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
         }
-        if (cands.empty())
-            for (int k = 1; k < K_COUNT; k++)
+        if (cands.empty()) {
+            for (int k = K_MFMA_S; k < K_COUNT; k++)
                 if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
+            // the VALU kernel only where no matrix-core tile applies or the step is tiny
+            if ((cands.empty() || rec.flops * (double)Sl < 1e9) && gemm_supported(K_SKINNY_N, dt, an.al, g))
+                cands.push_back(K_SKINNY_N);
+        }
         if (cands.size() <= 1) continue;
         TuneKey key((int)dt, (int)an.al, ilog2(g.M), ilog2(g.N), ilog2(g.K), ilog2(g.nb), g.a_kc, g.b_kc, g.c_nc);
         auto it = g_tune.find(key);
@@ -518,6 +536,7 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
     g.a_kc = rec.a_kc;
     g.b_kc = rec.b_kc;
     g.c_nc = rec.c_nc;
+    g.part = p->d_part;
     (void)es;
     ScaleRefs sc{};
     if (dt != Dtype::C64) {

@@ -52,6 +52,7 @@ struct tnc_plan {
     int64_t bits_cap = 0;
     double *d_acc = nullptr;
     int *d_qob = nullptr;
+    float2 *d_part = nullptr;            // split-K partial sums (largest need over the steps)
     std::vector<int> h_growth;
     std::vector<int64_t> closed_state;  // closed_off per leaf last uploaded
     // graph cache: (slices, bitstrings, bits pointer) -> executable graph

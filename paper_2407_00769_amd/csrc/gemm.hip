@@ -295,14 +295,18 @@ __global__ void __launch_bounds__(64 * WM * WN)
     extern __shared__ __align__(16) uint8_t smem[];
 
     const int s = blockIdx.z;
-    const int64_t b = blockIdx.y;
+    const int64_t P = g.split;
+    const int64_t b = blockIdx.y / P, part = blockIdx.y - b * P;
     const int64_t tiles_n = (g.N + BN - 1) / BN;
     const int64_t tiles_m = (g.M + BM - 1) / BM;
     const int64_t t = xcd_tile(blockIdx.x, tiles_m * tiles_n);
     const int64_t m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
-    int shift = step_shift(sc, s);
-    if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
-    const float scale = pow2_neg(shift);
+    float scale = 1.f;
+    if (P == 1) {
+        int shift = step_shift(sc, s);
+        if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
+        scale = pow2_neg(shift);
+    }
 
     const uint32_t *Ap = A + s * g.sA + b * g.bA;
     const uint32_t *Bp = B + s * g.sB + b * g.bB;
@@ -415,13 +419,16 @@ __global__ void __launch_bounds__(64 * WM * WN)
 #pragma unroll
                 for (int r = 0; r < 16; r++) acc[a][i][j][r] = 0.f;
 
-    const int64_t nk = (g.K + BK - 1) / BK;
-    gload(0);
+    // k tiles of this split part
+    const int64_t nk_all = (g.K + BK - 1) / BK;
+    const int64_t kt0 = nk_all * part / P, kt1 = nk_all * (part + 1) / P;
+    const int64_t nk = kt1 - kt0;
+    gload(kt0 * BK);
     sstore(0);
     __syncthreads();
     for (int64_t kt = 0; kt < nk; kt++) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if (kt + 1 < nk) gload((kt0 + kt + 1) * BK);
         const uint8_t *ab = a_base(buf), *bb = b_base(buf);
 #pragma unroll
         for (int kk = 0; kk < BK / Tl::KSTEP; kk++) {
@@ -471,6 +478,28 @@ __global__ void __launch_bounds__(64 * WM * WN)
             sstore(buf ^ 1);
             __syncthreads();
         }
+    }
+
+    if (P > 1) {
+        // split part: FP32 partial sums straight from the accumulators
+        float *pp = (float *)(g.part + ((s * g.nb + b) * P + part) * g.M * g.N);
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+            for (int j = 0; j < FN; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    int col = wn * WTN + j * 32 + (lane & 31);
+                    if constexpr (!M3) {
+                        // real column 2n + part of the interleaved complex row
+                        pp[(m0 + row) * 2 * g.N + 2 * n0 + col] = acc[0][i][j][r];
+                    } else {
+                        float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+                        ((float2 *)pp)[(m0 + row) * g.N + n0 + col] = make_float2(t1 - t2, t3 - t1 - t2);
+                    }
+                }
+        return;
     }
 
     // ---- epilogue: scale, round, stage the tile as complex words [BM][BN], write out
@@ -565,7 +594,8 @@ __global__ void __launch_bounds__(64 * WM * WN)
     auto Bs = [&](int buf) { return lds + 2 * BM * LDA + buf * (BN * LDB); };
 
     const int s = blockIdx.z;
-    const int64_t b = blockIdx.y;
+    const int64_t P = g.split;
+    const int64_t b = blockIdx.y / P, part = blockIdx.y - b * P;
     const int64_t tiles_n = (g.N + BN - 1) / BN;
     const int64_t tiles_m = (g.M + BM - 1) / BM;
     const int64_t t = xcd_tile(blockIdx.x, tiles_m * tiles_n);
@@ -655,15 +685,17 @@ __global__ void __launch_bounds__(64 * WM * WN)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
 
-    const int64_t nk = (g.K + BK - 1) / BK;
-    gload(0);
+    const int64_t nk_all = (g.K + BK - 1) / BK;
+    const int64_t kt0 = nk_all * part / P, kt1 = nk_all * (part + 1) / P;
+    const int64_t nk = kt1 - kt0;
+    gload(kt0 * BK);
     sstore(0);
     __syncthreads();
     const int c = lane >> 5;        // k' parity this lane feeds: 0 = re, 1 = im
     const int d = lane & 1;         // output column parity
     for (int64_t kt = 0; kt < nk; kt++) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if (kt + 1 < nk) gload((kt0 + kt + 1) * BK);
         const float2 *a = As(buf), *bb = Bs(buf);
 #pragma unroll 4
         for (int kk = 0; kk < BK; kk++) {
@@ -690,6 +722,20 @@ __global__ void __launch_bounds__(64 * WM * WN)
             sstore(buf ^ 1);
             __syncthreads();
         }
+    }
+    if (P > 1) {
+        float *pp = (float *)(g.part + ((s * g.nb + b) * P + part) * g.M * g.N);
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+            for (int j = 0; j < FN; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    int col = wn * WTN + j * 32 + (lane & 31);
+                    pp[(m0 + row) * 2 * g.N + 2 * n0 + col] = acc[i][j][r];
+                }
+        return;
     }
     float *Cs = (float *)smem;   // [BM][2*BN]
 #pragma unroll
@@ -719,6 +765,34 @@ __global__ void __launch_bounds__(64 * WM * WN)
             }
         }
     }
+}
+
+// ===================================================================== split-K reduction
+// C[m][n] = sum over parts p = 0..P-1 of part[p][m][n], in that order; then the
+// usual epilogue (scale, round, orientation, max, overflow flag).
+
+template <typename W, bool SCALE>
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(W *__restrict__ C, GemmShape g, ScaleRefs sc) {
+    const int s = blockIdx.z;
+    const int64_t b = blockIdx.y;
+    int shift = SCALE ? step_shift(sc, s) : 0;
+    if (SCALE && blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
+    const float scale = pow2_neg(shift);
+    const int64_t MN = g.M * g.N;
+    const float2 *pp = g.part + (s * g.nb + b) * g.split * MN;
+    W *Cp = C + s * g.sC + b * g.bC;
+    float mx = 0.f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < MN; i += (int64_t)gridDim.x * blockDim.x) {
+        float re = 0.f, im = 0.f;
+        for (int64_t p = 0; p < g.split; p++) {
+            float2 v = pp[p * MN + i];
+            re += v.x;
+            im += v.y;
+        }
+        const int64_t m = i / g.N, n = i - m * g.N;
+        mx = fmaxf(mx, store_entry<W, SCALE>(Cp + c_index(g, m, n), re, im, scale));
+    }
+    finish_max<SCALE>(sc, s, mx);
 }
 
 // ===================================================================== dispatch
@@ -843,7 +917,7 @@ static void launch_h_cfg(const void *A, const void *B, void *C, const GemmShape 
         attr = true;
     }
     int64_t tiles = (g.M / BM) * (g.N / BN);
-    dim3 grid((unsigned)tiles, (unsigned)g.nb, S);
+    dim3 grid((unsigned)tiles, (unsigned)(g.nb * g.split), S);
     hipLaunchKernelGGL(kern, grid, dim3(Tl::NT), Tl::LDS_BYTES, st, (const uint32_t *)A, (const uint32_t *)B,
                        (uint32_t *)C, g, sc);
 }
@@ -857,7 +931,7 @@ static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, co
             case K_MFMA_M: launch_h_cfg<BF, false, 128, 32, 32, 2, 2>(A, B, C, g, S, sc, st); break;
             case K_MFMA_L: launch_h_cfg<BF, false, 128, 64, 32, 2, 2>(A, B, C, g, S, sc, st); break;
             case K_MFMA_W: launch_h_cfg<BF, false, 256, 16, 32, 4, 1>(A, B, C, g, S, sc, st); break;
-            case K_MFMA_XL: launch_h_cfg<BF, false, 256, 128, 16, 2, 2>(A, B, C, g, S, sc, st); break;
+            case K_MFMA_XL: launch_h_cfg<BF, false, 256, 128, 32, 4, 2>(A, B, C, g, S, sc, st); break;
             case K_MFMA_L2: launch_h_cfg<BF, false, 128, 128, 32, 2, 2>(A, B, C, g, S, sc, st); break;
         }
     } else {
@@ -882,7 +956,7 @@ static void launch_c_cfg(const void *A, const void *B, void *C, const GemmShape 
         attr = true;
     }
     int64_t tiles = (g.M / BM) * (g.N / BN);
-    dim3 grid((unsigned)tiles, (unsigned)g.nb, S);
+    dim3 grid((unsigned)tiles, (unsigned)(g.nb * g.split), S);
     hipLaunchKernelGGL(kern, grid, dim3(Tl::NT), Tl::LDS_BYTES, st, (const float2 *)A, (const float2 *)B,
                        (float2 *)C, g);
 }
@@ -898,13 +972,51 @@ static void launch_c64(int kid, const void *A, const void *B, void *C, const Gem
     }
 }
 
-void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void *C, const GemmShape &g, int S,
+int64_t splitk_factor(int kid, Dtype dt, Algo al, const GemmShape &g, int S) {
+    if (kid < K_MFMA_S || kid >= K_COUNT || !gemm_supported(kid, dt, al, g)) return 1;
+    TileCfg t = tile_of(kid, dt, al);
+    const int64_t bk = dt == Dtype::C64 ? 16 : 32;
+    const int64_t blocks = (g.M / t.BM) * (g.N / t.BN) * g.nb * (int64_t)S;
+    const int64_t ktiles = g.K / bk;
+    if (blocks >= 512 || ktiles < 16) return 1;
+    int64_t p = 1;
+    while (p * 2 * blocks <= 1024 && p * 2 <= ktiles / 4 && g.nb * p * 2 <= 65535) p *= 2;
+    return p;
+}
+
+int64_t splitk_bytes(int kid, Dtype dt, Algo al, const GemmShape &g, int S) {
+    int64_t p = splitk_factor(kid, dt, al, g, S);
+    return p > 1 ? p * (int64_t)S * g.nb * g.M * g.N * (int64_t)sizeof(float2) : 0;
+}
+
+void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void *C, const GemmShape &g_in, int S,
                  const ScaleRefs *sc, hipStream_t st) {
     if (S <= 0) return;
-    if (!gemm_supported(kid, dt, al, g)) TNC_THROW(TNC_EINVAL, std::string("kernel ") + kernel_name(kid) + " cannot run this shape");
+    if (!gemm_supported(kid, dt, al, g_in)) TNC_THROW(TNC_EINVAL, std::string("kernel ") + kernel_name(kid) + " cannot run this shape");
     ScaleRefs none{};
     const ScaleRefs &s = sc ? *sc : none;
     if (dt != Dtype::C64 && !sc) TNC_THROW(TNC_EINVAL, "16-bit forms need scale bookkeeping");
+    GemmShape g = g_in;
+    g.split = g.part ? splitk_factor(kid, dt, al, g, S) : 1;
+    if (g.split > 1) {
+        if (dt == Dtype::C64)
+            launch_c64(kid, A, B, C, g, S, st);
+        else if (dt == Dtype::F16)
+            launch_h<false>(kid, al, A, B, C, g, S, s, st);
+        else
+            launch_h<true>(kid, al, A, B, C, g, S, s, st);
+        HIP_CHECK(hipGetLastError());
+        const int64_t MN = g.M * g.N;
+        dim3 grid((unsigned)std::min<int64_t>((MN + 255) / 256, 4096), (unsigned)g.nb, S);
+        if (dt == Dtype::C64)
+            hipLaunchKernelGGL((splitk_reduce_kernel<uint2, false>), grid, dim3(256), 0, st, (uint2 *)C, g, s);
+        else if (dt == Dtype::F16)
+            hipLaunchKernelGGL((splitk_reduce_kernel<HalfWord, true>), grid, dim3(256), 0, st, (HalfWord *)C, g, s);
+        else
+            hipLaunchKernelGGL((splitk_reduce_kernel<Bf16Word, true>), grid, dim3(256), 0, st, (Bf16Word *)C, g, s);
+        HIP_CHECK(hipGetLastError());
+        return;
+    }
     if (kid == K_NAIVE || kid == K_SKINNY_N) {
         if (dt == Dtype::C64)
             launch_valu<uint2, false>(kid, al, A, B, C, g, S, s, st);

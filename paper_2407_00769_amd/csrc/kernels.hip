@@ -70,23 +70,57 @@ __global__ void permute_naive_kernel(const W *__restrict__ src, W *__restrict__ 
     }
 }
 
-// Tiled variant: the 2^w lowest destination bits and the 2^w lowest source
-// bits form an LDS tile so both the HBM read and the HBM write are contiguous
-// runs of 2^w entries.  Host guarantees: rank >= 2w, the w lowest source bits
-// are destination bits in tb[w..2w) (distinct from the w lowest destination
-// bits), and every remaining destination bit is outside both sets.
-template <typename W, int LW>
+// Tiled variant: a tile is every combination of the tile bits T (the w
+// lowest destination bits and the destination bits holding the w lowest
+// source bits, grown to 12 bits with further low bits of either side); the
+// remaining bits select the tile.  The tile is read in
+// source order and written in destination order through LDS, so both HBM
+// streams are runs of at least 2^w entries; every thread moves 16-byte
+// chunks (VEC entries, contiguous in the source when read and in the
+// destination when written).  In-tile offsets depend only on the thread, so
+// they are computed once; the LDS index is XOR-swizzled so both the scattered
+// and the sequential accesses spread over the banks.
+template <typename W, int VEC>
 __global__ void __launch_bounds__(256) permute_tiled_kernel(const W *__restrict__ src, W *__restrict__ dst,
-                                                            PermuteDesc d, int64_t n_tiles,
-                                                            int64_t src_ss, const int64_t *__restrict__ soff,
-                                                            int64_t dst_ss, TileBits tb) {
-    constexpr int T = 1 << LW;
-    __shared__ W tile[T][T + 1];
+                                                            PermuteDesc d, int64_t n_tiles, int64_t src_ss,
+                                                            const int64_t *__restrict__ soff, int64_t dst_ss,
+                                                            TileBits tb) {
+    typedef W Vec __attribute__((ext_vector_type(VEC)));
+    constexpr int LV = VEC == 4 ? 2 : 1;
+    constexpr int TE = 1 << kPermTileBits;
+    constexpr int CPT = TE / VEC / 256;   // chunks per thread for the largest tile
+    __shared__ W tile[TE];
     const int s = blockIdx.y;
     const W *sp = src + s * src_ss + (soff ? soff[s] : 0);
     W *dp = dst + s * dst_ss;
+    const int te = 1 << tb.nt;
+    const int nch = te >> LV;
+    int64_t so_c[CPT], do_c[CPT];
+    int li_q[CPT][VEC];
+    for (int j = 0; j < CPT; j++) {
+        const int c = threadIdx.x + j * 256;
+        // read side: chunk c covers source-order indices c*VEC .. c*VEC+VEC-1
+        int64_t so = 0;
+        int li_c = 0;
+        for (int i = LV; i < tb.nt; i++)
+            if (((c << LV) >> i) & 1) {
+                so += d.src_stride[tb.src_order[i]];
+                li_c |= 1 << tb.lds_bit[i];
+            }
+        so_c[j] = so;
+        for (int q = 0; q < VEC; q++) {
+            int li = li_c;
+            for (int i = 0; i < LV; i++)
+                if ((q >> i) & 1) li |= 1 << tb.lds_bit[i];
+            li_q[j][q] = li ^ ((li >> 5) & 31);
+        }
+        // write side: chunk c covers destination-order indices c*VEC .. +VEC-1
+        int64_t dof = 0;
+        for (int i = LV; i < tb.nt; i++)
+            if (((c << LV) >> i) & 1) dof += (int64_t)1 << tb.dst_order[i];
+        do_c[j] = dof;
+    }
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        // destination offset and source offset of the tile's base (bits outside the tile)
         int64_t dbase = 0, sbase = 0;
         int64_t tt = t;
         for (int i = 0; i < tb.n_rest; i++) {
@@ -97,21 +131,27 @@ __global__ void __launch_bounds__(256) permute_tiled_kernel(const W *__restrict_
             }
             tt >>= 1;
         }
-        // read: x = source-fast index (dest bits tb.hi[x-bits]), y = dest-fast index
-        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
-            int x = e & (T - 1), y = e >> LW;
-            int64_t so = sbase + (int64_t)x;   // the LW lowest source bits, in order
-            for (int i = 0; i < LW; i++)
-                if ((y >> i) & 1) so += d.src_stride[i];
-            tile[y][x] = sp[so];
+#pragma unroll
+        for (int j = 0; j < CPT; j++) {
+            if (threadIdx.x + j * 256 < nch) {
+                Vec v = *(const Vec *)(sp + sbase + so_c[j]);
+#pragma unroll
+                for (int q = 0; q < VEC; q++) tile[li_q[j][q]] = v[q];
+            }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
-            int y = e & (T - 1), x = e >> LW;
-            int64_t dof = dbase + (int64_t)y;
-            for (int i = 0; i < LW; i++)
-                if ((x >> i) & 1) dof += (int64_t)1 << tb.hi[i];
-            dp[dof] = tile[y][x];
+#pragma unroll
+        for (int j = 0; j < CPT; j++) {
+            const int c = threadIdx.x + j * 256;
+            if (c < nch) {
+                Vec v;
+#pragma unroll
+                for (int q = 0; q < VEC; q++) {
+                    int e = (c << LV) + q;
+                    v[q] = tile[e ^ ((e >> 5) & 31)];
+                }
+                *(Vec *)(dp + dbase + do_c[j]) = v;
+            }
         }
         __syncthreads();
     }
@@ -122,15 +162,16 @@ void launch_permute(Dtype dt, const void *src, void *dst, const PermuteDesc &d, 
     if (n_out <= 0 || S <= 0) return;
     TileBits tb;
     const int LW = 5;
-    bool tiled = plan_tile_bits(d, LW, tb);
+    bool tiled = plan_tile_bits(d, LW, kPermTileBits, tb);
     if (tiled) {
-        int64_t n_tiles = n_out >> (2 * LW);
-        int g = grid_for(n_tiles, 1, 1 << 20);
+        int64_t n_tiles = n_out >> tb.nt;
+        int g = grid_for(n_tiles, 1, 8192);
         if (dt == Dtype::C64)
-            hipLaunchKernelGGL((permute_tiled_kernel<uint2, 5>), dim3(g, S), dim3(256), 0, st,
-                               (const uint2 *)src, (uint2 *)dst, d, n_tiles, src_ss, soff, dst_ss, tb);
+            hipLaunchKernelGGL((permute_tiled_kernel<unsigned long long, 2>), dim3(g, S), dim3(256), 0, st,
+                               (const unsigned long long *)src, (unsigned long long *)dst, d, n_tiles, src_ss, soff,
+                               dst_ss, tb);
         else
-            hipLaunchKernelGGL((permute_tiled_kernel<uint32_t, 5>), dim3(g, S), dim3(256), 0, st,
+            hipLaunchKernelGGL((permute_tiled_kernel<uint32_t, 4>), dim3(g, S), dim3(256), 0, st,
                                (const uint32_t *)src, (uint32_t *)dst, d, n_tiles, src_ss, soff, dst_ss, tb);
     } else {
         int g = grid_for(n_out, 256, 1 << 20);

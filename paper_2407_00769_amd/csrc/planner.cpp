@@ -32,26 +32,50 @@ PermuteDesc make_permute(const std::vector<int> &from, const std::vector<int> &t
     return d;
 }
 
-bool plan_tile_bits(const PermuteDesc &d, int lw, TileBits &tb) {
+bool plan_tile_bits(const PermuteDesc &d, int lw, int nt_max, TileBits &tb) {
     const int r = d.rank;
-    if (r < 2 * lw) return false;
-    // identity on the low bits: the plain kernel is already coalesced
-    int run = 0;
-    while (run < r && d.src_stride[run] == ((int64_t)1 << run)) run++;
-    if (run >= 4) return false;
-    bool in_tile[kMaxRank] = {false};
-    for (int b = 0; b < lw; b++) in_tile[b] = true;
-    for (int i = 0; i < lw; i++) {
-        int found = -1;
-        for (int b = 0; b < r; b++)
-            if (d.src_stride[b] == ((int64_t)1 << i)) found = b;
-        if (found < 0 || found < lw) return false;   // a low source bit is fixed or is also a low dest bit
-        tb.hi[i] = found;
-        in_tile[found] = true;
+    if (r < lw + 1) return false;
+    bool in_t[kMaxRank] = {false};
+    for (int b = 0; b < lw; b++) in_t[b] = true;
+    int nsrc = 0;
+    for (int b = 0; b < r; b++)
+        if (d.src_stride[b] < ((int64_t)1 << lw)) {
+            in_t[b] = true;
+            nsrc++;
+        }
+    if (nsrc != lw) return false;   // the lowest source bits are not all destination bits
+    int nt = 0;
+    for (int b = 0; b < r; b++) nt += in_t[b];
+    if (nt > nt_max) return false;
+    // grow T to nt_max bits, alternating the lowest destination bit and the
+    // lowest source bit still outside it: every tile then keeps all threads
+    // busy, and both HBM runs only get longer
+    bool take_dst = true;
+    while (nt < nt_max && nt < r) {
+        int pick = -1;
+        if (take_dst) {
+            for (int b = 0; b < r && pick < 0; b++)
+                if (!in_t[b]) pick = b;
+        } else {
+            for (int b = 0; b < r; b++)
+                if (!in_t[b] && (pick < 0 || d.src_stride[b] < d.src_stride[pick])) pick = b;
+        }
+        in_t[pick] = true;
+        nt++;
+        take_dst = !take_dst;
     }
+    tb.nt = 0;
+    for (int b = 0; b < r; b++)
+        if (in_t[b]) tb.dst_order[tb.nt++] = b;
+    // source order of the tile bits: by source stride
+    for (int i = 0; i < tb.nt; i++) tb.src_order[i] = tb.dst_order[i];
+    std::sort(tb.src_order, tb.src_order + tb.nt, [&](int x, int y) { return d.src_stride[x] < d.src_stride[y]; });
+    for (int i = 0; i < tb.nt; i++)
+        for (int j = 0; j < tb.nt; j++)
+            if (tb.dst_order[j] == tb.src_order[i]) tb.lds_bit[i] = j;
     tb.n_rest = 0;
     for (int b = 0; b < r; b++)
-        if (!in_tile[b]) tb.rest[tb.n_rest++] = b;
+        if (!in_t[b]) tb.rest[tb.n_rest++] = b;
     return true;
 }
 
@@ -210,6 +234,10 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         if (cnt != n_open) TNC_THROW(TNC_EINVAL, "an open output label never reaches the root");
     }
 
+    // step at which each label is summed (open outputs: never)
+    std::vector<int> kstep(L, n_steps + 1);
+    for (int s = 0; s < n_steps; s++)
+        for (int l : an.steps[s].k) kstep[l] = s;
     // layout pass: storage orders, operand orientations and permutes
     const int es = elem_bytes(an.dt);
     for (int s = 0; s < n_steps; s++) {
@@ -266,10 +294,13 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         // Z order: try both C orientations and both consumer orientations; free
         // internal orders (operands that are permuted or gathered) follow the
         // consumer's groups
+        // free orders follow the consumer's groups; within a group, labels summed
+        // later sit higher, so the stem keeps its soon-summed labels at the low end
         auto ranked = [&](std::vector<int> v, bool kfirst) {
             std::stable_sort(v.begin(), v.end(), [&](int p, int q) {
                 auto key = [&](int l) { return cg[l] == 0 ? 0 : (kfirst ? (cg[l] == 2 ? 1 : 2) : cg[l]); };
-                return key(p) < key(q);
+                if (key(p) != key(q)) return key(p) < key(q);
+                return kstep[p] > kstep[q];
             });
             return v;
         };
