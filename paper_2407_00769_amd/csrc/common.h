@@ -68,14 +68,34 @@ struct PermuteDesc {
     int64_t src_stride[kMaxRank];  // element stride in the source for destination bit b (bit 0 = fastest)
 };
 
+// Placement of one GEMM index in memory.  The index's labels lie in at most
+// two runs of consecutive bits: x = (hi << l) | lo with lo < 2^l, and
+//     offset(x) = (hi << hs) + (lo << ls)      (in entries).
+// A single run has l = 62 (hi is always 0).
+struct Seg {
+    int32_t l = 62, ls = 0, hs = 0;
+};
+__host__ __device__ inline int64_t seg_offset(const Seg &s, int64_t x) {
+    return ((x >> s.l) << s.hs) + ((x & (((int64_t)1 << s.l) - 1)) << s.ls);
+}
+// length of the run that holds index bit 0 (the run chunks are taken along)
+inline int seg_low_run(const Seg &s, int64_t extent) {
+    int b = 0;
+    while (((int64_t)1 << (b + 1)) <= extent) b++;
+    return s.l < b ? s.l : b;
+}
+
 // Everything one step needs at run time.  Sizes are complex entries.
-// Operand orientation: A is [m][k] (a_kc = 1) or [k][m]; B is [n][k]
-// (b_kc = 1) or [k][n]; C is written [m][n] (c_nc = 1) or [n][m].
+// Chunk direction: A is read in 16-byte chunks along k (a_kc = 1) or along m;
+// B along k (b_kc = 1) or along n; C is written along n (c_nc = 1) or along m.
+// Where each index lives is given by its Seg (am, ak, bn, bk, cm, cn); the
+// chunked index's low run must start at bit 0 (ls = 0).
 struct GemmShape {
     int64_t M, N, K, nb;        // rows, cols, reduced, inner batch
     int64_t sA, sB, sC;         // slice strides (0 = shared by every slice)
     int64_t bA, bB, bC;         // inner-batch strides
     int a_kc = 1, b_kc = 1, c_nc = 1, pad_ = 0;
+    Seg am, ak, bn, bk, cm, cn;
     // split-K: the reduced range is cut into `split` parts; each part's FP32
     // partial result goes to part[((s * nb + b) * split + p)][m][n] (re, im
     // pairs) and a second kernel sums the parts in order
@@ -109,9 +129,14 @@ enum KernelId : int {
     K_MFMA_W = 5,     // tall thin tile
     K_MFMA_XL = 6,    // large tiles for compute-bound steps
     K_MFMA_L2 = 7,
-    K_COUNT = 8
+    K_DMA_4 = 8,      // 16-bit 4M, operands streamed into LDS by DMA; 4 waves
+    K_DMA_8 = 9,      // the same with 8 waves
+    K_COUNT = 10
 };
 const char *kernel_name(int k);
+// Segments of the plain layouts ([m][k] or [k][m] etc., as the chunk flags
+// say); M, N, K must be powers of two.
+void set_plain_segs(GemmShape &g);
 
 // Launch wrappers (kernels.hip).
 void launch_permute(Dtype dt, const void *src, void *dst, const PermuteDesc &d, int64_t n_out,

@@ -11,17 +11,6 @@ using namespace tnc;
 
 namespace {
 
-bool grouped3(const std::vector<int> &order, const std::vector<int> &g0, const std::vector<int> &g1,
-              const std::vector<int> &g2) {
-    if (order.size() != g0.size() + g1.size() + g2.size()) return false;
-    size_t p = 0;
-    for (const auto *g : {&g0, &g1, &g2}) {
-        for (size_t i = 0; i < g->size(); i++, p++)
-            if (std::find(g->begin(), g->end(), order[p]) == g->end()) return false;
-    }
-    return true;
-}
-
 std::vector<int> keep_order(const std::vector<int> &order, const std::vector<int> &set) {
     std::vector<int> r;
     for (int l : order)
@@ -72,70 +61,72 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
             if (!has(la, l) && !has(lb, l)) TNC_THROW(TNC_EINVAL, "label of C is in neither operand");
         if (dt == Dtype::C64 && al == Algo::M3) TNC_THROW(TNC_EINVAL, "3M needs 16-bit storage");
 
-        // roles: rows operand R (its free labels are the GEMM rows), cols operand
+        // roles: rows operand R (the one with more free labels), cols operand Q
         const void *R = A, *Q = B;
         std::vector<int> lr = la, lq = lb, fr = m, fq = n;
-        bool direct = false;
-        std::vector<int> bo, mo, no;
-        if (grouped3(lc, beta, m, n)) {
-            direct = true;
-        } else if (grouped3(lc, beta, n, m)) {
-            direct = true;
-            std::swap(R, Q);
-            std::swap(lr, lq);
-            std::swap(fr, fq);
-        } else if (n.size() > m.size()) {
+        if (n.size() > m.size()) {
             std::swap(R, Q);
             std::swap(lr, lq);
             std::swap(fr, fq);
         }
-        if (direct) {
-            bo = keep_order(lc, beta);
-            mo = keep_order(lc, fr);
-            no = keep_order(lc, fq);
-        } else {
-            bo = keep_order(lr, beta);
-            mo = keep_order(lr, fr);
-            no = keep_order(lq, fq);
-        }
-        std::vector<int> ko = keep_order(lr, k);
-        // operands keep their layout when it reads as [batch][free][k] or [batch][k][free]
-        auto fits = [&](const std::vector<int> &l, const std::vector<int> &fo, int &kc) {
-            if (l == cat({&bo, &fo, &ko})) { kc = 1; return true; }
-            if (l == cat({&bo, &ko, &fo})) { kc = 0; return true; }
-            return false;
+        // Index orders.  A tensor is used in place when its batch labels form
+        // the top block in the batch order and each of its two GEMM indices
+        // lies in at most two runs, the lowest run holding a whole 16-byte
+        // chunk; otherwise it is permuted to (or from) [batch][i1][i2].  Every
+        // choice of orders taken from the tensors is tried; the one that
+        // permutes the fewest bytes wins.
+        const int lq_bits = dt == Dtype::C64 ? 1 : 2;
+        struct Side {
+            bool inplace = false;
+            int kc = 1;
+            Seg s1, s2;
         };
-        int r_kc = 1, q_kc = 1;
-        if (!direct) {
-            // free orders are ours to choose: take them from the operands
-            mo = keep_order(lr, fr);
-            no = keep_order(lq, fq);
-        }
-        bool keep_r = fits(lr, mo, r_kc);
-        if (!keep_r) r_kc = 1;
-        if (!fits(lq, no, q_kc)) {
-            // try B's own k order (then R may need the permute instead)
-            std::vector<int> ko2 = keep_order(lq, k);
-            std::vector<int> save = ko;
-            ko = ko2;
-            int t1 = 1, t2 = 1;
-            if (fits(lq, no, t2) && !keep_r) {
-                q_kc = t2;
-            } else {
-                ko = save;
-                q_kc = 1;
+        auto check = [&](const std::vector<int> &order, const std::vector<int> &bo, const std::vector<int> &i1,
+                         const std::vector<int> &i2, Side &sd) {
+            sd = Side{};
+            if (!std::equal(bo.begin(), bo.end(), order.begin())) return;
+            Seg s1, s2;
+            if (!derive_seg(order, i1, s1) || !derive_seg(order, i2, s2)) return;
+            if (order.size() == bo.size()) {   // batch only
+                sd = Side{true, 1, s1, s2};
+                return;
             }
-            (void)t1;
-        }
-        std::vector<int> want_r = r_kc ? cat({&bo, &mo, &ko}) : cat({&bo, &ko, &mo});
-        std::vector<int> want_q = q_kc ? cat({&bo, &no, &ko}) : cat({&bo, &ko, &no});
-        std::vector<int> gemm_c = cat({&bo, &mo, &no});
-        std::vector<int> gemm_ct = cat({&bo, &no, &mo});
-        int c_nc = 1;
-        if (gemm_c != lc && gemm_ct == lc) c_nc = 0;
-        const bool perm_r = want_r != lr, perm_q = want_q != lq, perm_c = (c_nc ? gemm_c : gemm_ct) != lc;
-        const int es = elem_bytes(dt);
+            const bool low2 = has(i2, order.back());
+            const Seg &cs = low2 ? s2 : s1;
+            const int64_t ext = (int64_t)1 << (low2 ? i2.size() : i1.size());
+            if (cs.ls != 0 || seg_low_run(cs, ext) < lq_bits) return;
+            sd = Side{true, low2 ? 1 : 0, s1, s2};
+        };
         const int64_t nr = (int64_t)1 << lr.size(), nq = (int64_t)1 << lq.size(), nc = (int64_t)1 << lc.size();
+        std::vector<int> bo, mo, no, ko;
+        Side sr, sq, sc_;
+        double best = -1;
+        for (const auto *bsrc : {&lc, &lr, &lq})
+            for (const auto *msrc : {&lr, &lc})
+                for (const auto *nsrc : {&lq, &lc})
+                    for (const auto *ksrc : {&lr, &lq}) {
+                        std::vector<int> b1 = keep_order(*bsrc, beta), m1 = keep_order(*msrc, fr),
+                                         n1 = keep_order(*nsrc, fq), k1 = keep_order(*ksrc, k);
+                        Side x, y, z;
+                        check(lr, b1, m1, k1, x);
+                        check(lq, b1, n1, k1, y);
+                        check(lc, b1, m1, n1, z);
+                        double cost = (x.inplace ? 0.0 : (double)nr) + (y.inplace ? 0.0 : (double)nq) +
+                                      (z.inplace ? 0.0 : (double)nc);
+                        if (best < 0 || cost < best) {
+                            best = cost;
+                            bo = b1;
+                            mo = m1;
+                            no = n1;
+                            ko = k1;
+                            sr = x;
+                            sq = y;
+                            sc_ = z;
+                        }
+                    }
+        std::vector<int> want_r = cat({&bo, &mo, &ko}), want_q = cat({&bo, &no, &ko}), gemm_c = cat({&bo, &mo, &no});
+        const bool perm_r = !sr.inplace, perm_q = !sq.inplace, perm_c = !sc_.inplace;
+        const int es = elem_bytes(dt);
         auto al256 = [](int64_t v) { return (v + 255) & ~(int64_t)255; };
         int64_t off = 0, off_r = 0, off_q = 0, off_c = 0;
         if (perm_r) { off_r = off; off += al256(nr * es); }
@@ -189,9 +180,22 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
         g.bA = g.M * g.K;
         g.bB = g.N * g.K;
         g.bC = g.M * g.N;
-        g.a_kc = r_kc;
-        g.b_kc = q_kc;
-        g.c_nc = c_nc;
+        g.a_kc = perm_r ? 1 : sr.kc;
+        g.b_kc = perm_q ? 1 : sq.kc;
+        g.c_nc = perm_c ? 1 : sc_.kc;
+        set_plain_segs(g);
+        if (!perm_r) {
+            g.am = sr.s1;
+            g.ak = sr.s2;
+        }
+        if (!perm_q) {
+            g.bn = sq.s1;
+            g.bk = sq.s2;
+        }
+        if (!perm_c) {
+            g.cm = sc_.s1;
+            g.cn = sc_.s2;
+        }
         void *pc = perm_c ? (void *)(ctx->ws + off_c) : C;
         int kid = choose_kernel(dt, al, g);
         const char *force = getenv("TNC_FORCE_KERNEL");
@@ -204,7 +208,7 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
         if (pb > 0 && (size_t)(off + pb) <= ctx->ws_bytes) g.part = (float2 *)(ctx->ws + off);
         launch_gemm(kid, dt, al, pr, pq, pc, g, 1, dt != Dtype::C64 ? &sc : nullptr, st);
         HIP_CHECK(hipEventRecord(ev[3], st));
-        if (perm_c) launch_permute(dt, pc, C, make_permute(c_nc ? gemm_c : gemm_ct, lc), nc, 1, 0, nullptr, 0, st);
+        if (perm_c) launch_permute(dt, pc, C, make_permute(gemm_c, lc), nc, 1, 0, nullptr, 0, st);
         HIP_CHECK(hipEventRecord(ev[4], st));
         HIP_CHECK(hipEventSynchronize(ev[4]));
         if (times_ms) {

@@ -278,10 +278,10 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
     int64_t part_bytes = 0;
     for (const auto &rec : an.steps) {
         const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
-        GemmShape g{rec.M, rec.N, rec.K, rec.nb, A.dep ? 1 : 0, B.dep ? 1 : 0, 1, 0, 0, 0};
-        g.a_kc = rec.a_kc;
-        g.b_kc = rec.b_kc;
-        g.c_nc = rec.c_nc;
+        GemmShape g = step_gemm(rec);
+        g.sA = A.dep ? 1 : 0;
+        g.sB = B.dep ? 1 : 0;
+        g.sC = 1;
         (void)Z;
         for (int k = K_MFMA_S; k < K_COUNT; k++)
             part_bytes = std::max(part_bytes, splitk_bytes(k, dt, an.al, g, rec.dep ? S : 1));
@@ -371,17 +371,16 @@ double autotune_plan(tnc_plan *p) {
     for (auto &rec : an.steps) {
         const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
         const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank(), nz = (int64_t)1 << Z.rank();
-        GemmShape g{rec.M, rec.N, rec.K, rec.nb, A.dep ? na : 0, B.dep ? nbb : 0, nz, rec.M * rec.K, rec.N * rec.K,
-                    rec.M * rec.N};
-        g.a_kc = rec.a_kc;
-        g.b_kc = rec.b_kc;
-        g.c_nc = rec.c_nc;
+        GemmShape g = step_gemm(rec);
+        g.sA = A.dep ? na : 0;
+        g.sB = B.dep ? nbb : 0;
+        g.sC = nz;
         g.part = p->d_part;
         const int Sl = rec.dep ? p->S : 1;
         std::vector<int> cands;
         // big steps: only the large matrix-core tiles are worth timing
         const bool big = rec.flops * (double)Sl > 1e13;
-        static const int big_order[] = {K_MFMA_XL, K_MFMA_L2, K_MFMA_L};
+        static const int big_order[] = {K_DMA_8, K_DMA_4, K_MFMA_XL, K_MFMA_L2, K_MFMA_L};
         if (big) {
             for (int k : big_order)
                 if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
@@ -531,11 +530,10 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
         }
         pb = ws + rec.scr_b;
     }
-    GemmShape g{rec.M, rec.N, rec.K, rec.nb, A.dep ? na : 0, B.dep ? nbb : 0, nz, rec.M * rec.K, rec.N * rec.K,
-                rec.M * rec.N};
-    g.a_kc = rec.a_kc;
-    g.b_kc = rec.b_kc;
-    g.c_nc = rec.c_nc;
+    GemmShape g = step_gemm(rec);
+    g.sA = A.dep ? na : 0;
+    g.sB = B.dep ? nbb : 0;
+    g.sC = nz;
     g.part = p->d_part;
     (void)es;
     ScaleRefs sc{};

@@ -69,13 +69,13 @@ __device__ __forceinline__ float pow2_neg(int shift) {
 }
 
 __device__ __forceinline__ int64_t a_index(const GemmShape &g, int64_t m, int64_t k) {
-    return g.a_kc ? m * g.K + k : k * g.M + m;
+    return seg_offset(g.am, m) + seg_offset(g.ak, k);
 }
 __device__ __forceinline__ int64_t b_index(const GemmShape &g, int64_t n, int64_t k) {
-    return g.b_kc ? n * g.K + k : k * g.N + n;
+    return seg_offset(g.bn, n) + seg_offset(g.bk, k);
 }
 __device__ __forceinline__ int64_t c_index(const GemmShape &g, int64_t m, int64_t n) {
-    return g.c_nc ? m * g.N + n : n * g.M + m;
+    return seg_offset(g.cm, m) + seg_offset(g.cn, n);
 }
 
 // ===================================================================== naive: thread per output
@@ -241,7 +241,19 @@ template <bool BF> __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, 
                                                       __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
 }
 
-__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
+
+// 4M padding of B in registers, without branches: lane parity d picks
+// (br, -bi) (d = 0: keep the halves, flip the sign of the high one) or
+// (bi, br) (d = 1: swap the halves) through a byte permute and an XOR
+struct Pad4M {
+    uint32_t sel, mask;
+    __device__ explicit Pad4M(int d) : sel(d ? 0x01000302u : 0x03020100u), mask(d ? 0u : 0x80000000u) {}
+    __device__ __forceinline__ u32x4 operator()(u32x4 v) const {
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[q] = __builtin_amdgcn_perm(v[q], v[q], sel) ^ mask;
+        return v;
+    }
+};
 
 // rounded re + im of a 16-bit complex word, as 16-bit bits
 template <bool BF> __device__ __forceinline__ uint32_t sum_bits(uint32_t w) {
@@ -325,11 +337,11 @@ __global__ void __launch_bounds__(64 * WM * WN)
                 if (g.a_kc) {
                     int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
                     int64_t gm = m0 + row, gk = k0 + col;
-                    if (gm < g.M && gk < g.K) v = *(const u32x4 *)(Ap + gm * g.K + gk);
+                    if (gm < g.M && gk < g.K) v = *(const u32x4 *)(Ap + a_index(g, gm, gk));
                 } else {
                     int kr = c / (BM / 4), mc = (c % (BM / 4)) * 4;
                     int64_t gk = k0 + kr, gm = m0 + mc;
-                    if (gk < g.K && gm < g.M) v = *(const u32x4 *)(Ap + gk * g.M + gm);
+                    if (gk < g.K && gm < g.M) v = *(const u32x4 *)(Ap + a_index(g, gm, gk));
                 }
             }
             ra[i] = v;
@@ -342,11 +354,11 @@ __global__ void __launch_bounds__(64 * WM * WN)
                 if (g.b_kc) {
                     int row = c / (BK / 4), col = (c % (BK / 4)) * 4;
                     int64_t gn = n0 + row, gk = k0 + col;
-                    if (gn < g.N && gk < g.K) v = *(const u32x4 *)(Bp + gn * g.K + gk);
+                    if (gn < g.N && gk < g.K) v = *(const u32x4 *)(Bp + b_index(g, gn, gk));
                 } else {
                     int kr = c / (BN / 4), nc = (c % (BN / 4)) * 4;
                     int64_t gk = k0 + kr, gn = n0 + nc;
-                    if (gk < g.K && gn < g.N) v = *(const u32x4 *)(Bp + gk * g.N + gn);
+                    if (gk < g.K && gn < g.N) v = *(const u32x4 *)(Bp + b_index(g, gn, gk));
                 }
             }
             rb[i] = v;
@@ -435,20 +447,13 @@ __global__ void __launch_bounds__(64 * WM * WN)
             if constexpr (!M3) {
                 const uint32_t *As = (const uint32_t *)ab, *Bs = (const uint32_t *)bb;
                 const int kq = kk * 8 + (lane >> 5) * 4;
-                const int d = lane & 1;
+                const Pad4M pad(lane & 1);
                 u32x4 af[FM], bf[FN];
 #pragma unroll
                 for (int i = 0; i < FM; i++) af[i] = *(const u32x4 *)(As + (wm * WTM + i * 32 + (lane & 31)) * LDA + kq);
 #pragma unroll
                 for (int j = 0; j < FN; j++) {
-                    u32x4 v = *(const u32x4 *)(Bs + ((wn * WTN + j * 32 + (lane & 31)) >> 1) * LDB + kq);
-                    if (d == 0) {   // (br, -bi)
-                        v[0] ^= 0x80000000u; v[1] ^= 0x80000000u; v[2] ^= 0x80000000u; v[3] ^= 0x80000000u;
-                    } else {        // (bi, br)
-                        v[0] = swap_halves(v[0]); v[1] = swap_halves(v[1]);
-                        v[2] = swap_halves(v[2]); v[3] = swap_halves(v[3]);
-                    }
-                    bf[j] = v;
+                    bf[j] = pad(*(const u32x4 *)(Bs + ((wn * WTN + j * 32 + (lane & 31)) >> 1) * LDB + kq));
                 }
 #pragma unroll
                 for (int i = 0; i < FM; i++)
@@ -542,13 +547,13 @@ __global__ void __launch_bounds__(64 * WM * WN)
             int row = c / (BN / 4), col = (c % (BN / 4)) * 4;
             v = *(const u32x4 *)(Cw + row * BN + col);
             ok = (m0 + row) < g.M && (n0 + col) < g.N;
-            off = (m0 + row) * g.N + n0 + col;
+            off = c_index(g, m0 + row, n0 + col);
         } else {
             int col = c / (BM / 4), row = (c % (BM / 4)) * 4;
 #pragma unroll
             for (int q = 0; q < 4; q++) v[q] = Cw[(row + q) * BN + col];
             ok = (m0 + row) < g.M && (n0 + col) < g.N;
-            off = (n0 + col) * g.M + m0 + row;
+            off = c_index(g, m0 + row, n0 + col);
         }
         if (ok) {
             *(u32x4 *)(Cp + off) = v;
@@ -557,6 +562,207 @@ __global__ void __launch_bounds__(64 * WM * WN)
                 float2 f = unpack(W{v[q]});
                 mx = fmaxf(mx, absmax_nan(f.x, f.y));
             }
+        }
+    }
+    finish_max<true>(sc, s, mx);
+}
+
+// ===================================================================== matrix cores, 16-bit 4M, LDS DMA
+//
+// The compute-bound steps: both operands chunked along k, whole tiles.  The
+// operands go from global memory straight into a ring of STAGES LDS buffers
+// (global_load_lds_dwordx4 writes lane j's 16 bytes at base + 16 j), so no
+// registers stage them and up to STAGES-1 k-tiles are in flight while the
+// matrix cores work on the oldest.  An LDS row is one operand row's 32
+// complex k (128 bytes, 8 chunks); chunk q of row r sits in slot q ^ (r & 7),
+// so the DMA (whole rows) and the fragment reads (8 rows, one chunk each) are
+// both free of bank conflicts.  Fragments and the 4M padding of B are as in
+// gemm_mfma_h_kernel.
+
+// s_waitcnt vmcnt(VM) lgkmcnt(0), expcnt untouched (gfx9 field layout), as a
+// compiler barrier for memory too
+template <int VM> __device__ __forceinline__ void ring_wait() {
+    static_assert(VM >= 0 && VM < 64, "vmcnt");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int BM, int BN, int WM, int WN, int STAGES>
+struct DTile {
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int BK = 32;                               // complex k per stage
+    static constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
+    static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
+    static constexpr int RING_BYTES = STAGES * STAGE_BYTES;
+    static constexpr int C_BYTES = BM * BN * 4;
+    static constexpr int LDS_BYTES = RING_BYTES > C_BYTES ? RING_BYTES : C_BYTES;
+    static constexpr int WTM = BM / WM, WTN = 2 * BN / WN;       // rows, real columns per wave
+    static constexpr int FM = WTM / 32, FN = WTN / 32;
+    static constexpr int A_PER = BM / 8 / (NT / 64);             // 1 KB DMA blocks per wave and stage
+    static constexpr int B_PER = BN / 8 / (NT / 64);
+    static constexpr int LPT = A_PER + B_PER;                    // DMA loads per thread and stage
+    static_assert(FM >= 1 && FN >= 1, "wave tile too small");
+    static_assert(A_PER >= 1 && B_PER >= 1 && A_PER * (NT / 64) * 8 == BM && B_PER * (NT / 64) * 8 == BN, "DMA split");
+    static_assert(STAGES >= 2 && LPT * (STAGES - 2) < 64, "stages");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+template <int VM_AHEAD, int LPT> __device__ __forceinline__ void ring_wait_for(int64_t ahead) {
+    // stage kt is complete once at most `ahead` later stages are outstanding
+    if constexpr (VM_AHEAD == 0) {
+        ring_wait<0>();
+    } else {
+        if (ahead >= VM_AHEAD) ring_wait<VM_AHEAD * LPT>();
+        else ring_wait_for<VM_AHEAD - 1, LPT>(ahead);
+    }
+}
+
+template <bool BF, int BM, int BN, int WM, int WN, int STAGES>
+__global__ void __launch_bounds__(64 * WM * WN)
+    gemm_dma_h_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t *__restrict__ C,
+                      GemmShape g, ScaleRefs sc) {
+    using Tl = DTile<BM, BN, WM, WN, STAGES>;
+    using W = typename std::conditional<BF, Bf16Word, HalfWord>::type;
+    constexpr int NT = Tl::NT, FM = Tl::FM, FN = Tl::FN, WTM = Tl::WTM, WTN = Tl::WTN, BK = Tl::BK;
+    extern __shared__ __align__(16) uint8_t smem[];
+
+    const int s = blockIdx.z;
+    const int64_t P = g.split;
+    const int64_t b = blockIdx.y / P, part = blockIdx.y - b * P;
+    const int64_t tiles_n = g.N / BN, tiles_m = g.M / BM;
+    const int64_t t = xcd_tile(blockIdx.x, tiles_m * tiles_n);
+    const int64_t m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
+    float scale = 1.f;
+    if (P == 1) {
+        int shift = step_shift(sc, s);
+        if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
+        scale = pow2_neg(shift);
+    }
+    const uint32_t *Ap = A + s * g.sA + b * g.bA;
+    const uint32_t *Bp = B + s * g.sB + b * g.bB;
+    uint32_t *Cp = C + s * g.sC + b * g.bC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+
+    // DMA: wave w fills 1 KB blocks w, w + NT/64, ... of each operand; lane j
+    // of a block writes row 8 * block + j / 8, slot j % 8, which holds chunk
+    // q = (j % 8) ^ (j / 8) of that row
+    const int dq = (lane & 7) ^ (lane >> 3);
+    int64_t arow[Tl::A_PER], brow[Tl::B_PER];
+#pragma unroll
+    for (int i = 0; i < Tl::A_PER; i++) arow[i] = seg_offset(g.am, m0 + 8 * (wave + i * (NT / 64)) + (lane >> 3));
+#pragma unroll
+    for (int i = 0; i < Tl::B_PER; i++) brow[i] = seg_offset(g.bn, n0 + 8 * (wave + i * (NT / 64)) + (lane >> 3));
+    const int64_t nk_all = g.K / BK;
+    const int64_t kt0 = nk_all * part / P, kt1 = nk_all * (part + 1) / P;
+    const int64_t nk = kt1 - kt0;
+    auto issue = [&](int64_t kt) {
+        uint8_t *base = smem + (kt % STAGES) * Tl::STAGE_BYTES;
+        const int64_t k = (kt0 + kt) * BK + 4 * dq;
+        const int64_t ka = seg_offset(g.ak, k), kb = seg_offset(g.bk, k);
+#pragma unroll
+        for (int i = 0; i < Tl::A_PER; i++)
+            __builtin_amdgcn_global_load_lds((const void *)(Ap + arow[i] + ka),
+                                             (__attribute__((address_space(3))) void *)(base + (wave + i * (NT / 64)) * 1024),
+                                             16, 0, 0);
+#pragma unroll
+        for (int i = 0; i < Tl::B_PER; i++)
+            __builtin_amdgcn_global_load_lds((const void *)(Bp + brow[i] + kb),
+                                             (__attribute__((address_space(3))) void *)(base + Tl::A_BYTES +
+                                                                                        (wave + i * (NT / 64)) * 1024),
+                                             16, 0, 0);
+    };
+
+    floatx16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+
+    // fragment addresses: A row wm*WTM + 32i + lane%32 (row & 7 = lane & 7);
+    // B complex row (wn*WTN + 32j + lane%32) / 2 (row & 7 = (lane >> 1) & 7)
+    const int a_s0 = (lane >> 5) ^ (lane & 7), b_s0 = (lane >> 5) ^ ((lane >> 1) & 7);
+    const int a_row0 = (wm * WTM + (lane & 31)) * 128;
+    const int b_row0 = ((wn * WTN + (lane & 31)) >> 1) * 128;
+    const Pad4M pad(lane & 1);
+
+#pragma unroll
+    for (int st = 0; st < STAGES - 1; st++)
+        if (st < nk) issue(st);
+    for (int64_t kt = 0; kt < nk; kt++) {
+        ring_wait_for<STAGES - 2, Tl::LPT>(nk - 1 - kt);
+        if (kt + STAGES - 1 < nk) issue(kt + STAGES - 1);
+        const uint8_t *ab = smem + (kt % STAGES) * Tl::STAGE_BYTES;
+        const uint8_t *bb = ab + Tl::A_BYTES;
+#pragma unroll
+        for (int kk = 0; kk < BK / 8; kk++) {
+            u32x4 af[FM], bf[FN];
+            const int as = ((kk << 1) ^ a_s0) * 16, bs = ((kk << 1) ^ b_s0) * 16;
+#pragma unroll
+            for (int i = 0; i < FM; i++) af[i] = *(const u32x4 *)(ab + a_row0 + i * 32 * 128 + as);
+#pragma unroll
+            for (int j = 0; j < FN; j++) bf[j] = pad(*(const u32x4 *)(bb + b_row0 + j * 16 * 128 + bs));
+#pragma unroll
+            for (int i = 0; i < FM; i++)
+#pragma unroll
+                for (int j = 0; j < FN; j++) acc[i][j] = mfma16<BF>(af[i], bf[j], acc[i][j]);
+        }
+    }
+    ring_wait<0>();   // every wave is done with the ring before it is reused
+
+    if (P > 1) {
+        float *pp = (float *)(g.part + ((s * g.nb + b) * P + part) * g.M * g.N);
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+            for (int j = 0; j < FN; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    int col = wn * WTN + j * 32 + (lane & 31);
+                    pp[(m0 + row) * 2 * g.N + 2 * n0 + col] = acc[i][j][r];
+                }
+        return;
+    }
+    // epilogue: scale, round, stage the tile as complex words [BM][BN], write out
+    uint16_t *Ch = (uint16_t *)smem;
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                int col = wn * WTN + j * 32 + (lane & 31);
+                float v = acc[i][j][r] * scale;
+                Ch[row * (2 * BN) + col] = (uint16_t)(BF ? f2bf_bits(v) : f2h_bits(v));
+            }
+    __syncthreads();
+    const uint32_t *Cw = (const uint32_t *)smem;
+    float mx = 0.f;
+    constexpr int C_CHUNKS = BM * BN / 4;
+    for (int c = tid; c < C_CHUNKS; c += NT) {
+        u32x4 v;
+        int row, col;
+        if (g.c_nc) {
+            row = c / (BN / 4);
+            col = (c % (BN / 4)) * 4;
+            v = *(const u32x4 *)(Cw + row * BN + col);
+        } else {
+            col = c / (BM / 4);
+            row = (c % (BM / 4)) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; q++) v[q] = Cw[(row + q) * BN + col];
+        }
+        *(u32x4 *)(Cp + c_index(g, m0 + row, n0 + col)) = v;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            float2 f = unpack(W{v[q]});
+            mx = fmaxf(mx, absmax_nan(f.x, f.y));
         }
     }
     finish_max<true>(sc, s, mx);
@@ -616,11 +822,11 @@ __global__ void __launch_bounds__(64 * WM * WN)
                 if (g.a_kc) {
                     int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
                     int64_t gm = m0 + row, gk = k0 + col;
-                    if (gm < g.M && gk < g.K) v = *(const float4 *)(Ap + gm * g.K + gk);
+                    if (gm < g.M && gk < g.K) v = *(const float4 *)(Ap + a_index(g, gm, gk));
                 } else {
                     int kr = c / (BM / 2), mc = (c % (BM / 2)) * 2;
                     int64_t gk = k0 + kr, gm = m0 + mc;
-                    if (gk < g.K && gm < g.M) v = *(const float4 *)(Ap + gk * g.M + gm);
+                    if (gk < g.K && gm < g.M) v = *(const float4 *)(Ap + a_index(g, gm, gk));
                 }
             }
             ra[i] = v;
@@ -633,11 +839,11 @@ __global__ void __launch_bounds__(64 * WM * WN)
                 if (g.b_kc) {
                     int row = c / (BK / 2), col = (c % (BK / 2)) * 2;
                     int64_t gn = n0 + row, gk = k0 + col;
-                    if (gn < g.N && gk < g.K) v = *(const float4 *)(Bp + gn * g.K + gk);
+                    if (gn < g.N && gk < g.K) v = *(const float4 *)(Bp + b_index(g, gn, gk));
                 } else {
                     int kr = c / (BN / 2), nc = (c % (BN / 2)) * 2;
                     int64_t gk = k0 + kr, gn = n0 + nc;
-                    if (gk < g.K && gn < g.N) v = *(const float4 *)(Bp + gk * g.N + gn);
+                    if (gk < g.K && gn < g.N) v = *(const float4 *)(Bp + b_index(g, gn, gk));
                 }
             }
             rb[i] = v;
@@ -754,14 +960,14 @@ __global__ void __launch_bounds__(64 * WM * WN)
         if (g.c_nc) {
             int row = cc / (BN / 2), col = (cc % (BN / 2)) * 2;
             int64_t gm = m0 + row, gn = n0 + col;
-            if (gm < g.M && gn < g.N) *(float4 *)(Cp + gm * g.N + gn) = *(const float4 *)(Cs + row * 2 * BN + 2 * col);
+            if (gm < g.M && gn < g.N) *(float4 *)(Cp + c_index(g, gm, gn)) = *(const float4 *)(Cs + row * 2 * BN + 2 * col);
         } else {
             int col = cc / (BM / 2), row = (cc % (BM / 2)) * 2;
             int64_t gm = m0 + row, gn = n0 + col;
             if (gm < g.M && gn < g.N) {
                 float2 v0 = *(const float2 *)(Cs + row * 2 * BN + 2 * col);
                 float2 v1 = *(const float2 *)(Cs + (row + 1) * 2 * BN + 2 * col);
-                *(float4 *)(Cp + gn * g.M + gm) = make_float4(v0.x, v0.y, v1.x, v1.y);
+                *(float4 *)(Cp + c_index(g, gm, gn)) = make_float4(v0.x, v0.y, v1.x, v1.y);
             }
         }
     }
@@ -807,6 +1013,8 @@ const char *kernel_name(int k) {
         case K_MFMA_W: return "mfma_w";
         case K_MFMA_XL: return "mfma_xl";
         case K_MFMA_L2: return "mfma_l2";
+        case K_DMA_4: return "dma_4";
+        case K_DMA_8: return "dma_8";
         default: return "?";
     }
 }
@@ -833,6 +1041,8 @@ static TileCfg tile_of(int kid, Dtype dt, Algo al) {
             case K_MFMA_W: return {256, 16};
             case K_MFMA_XL: return {256, 128};
             case K_MFMA_L2: return {128, 128};
+            case K_DMA_4: return {256, 128};
+            case K_DMA_8: return {256, 128};
         }
     } else {
         switch (kid) {
@@ -857,12 +1067,21 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
     if (g.nb > 65535) return false;
     if (kid < 0 || kid >= K_COUNT) return false;
     if (dt == Dtype::C64 && al == Algo::M3) return false;
+    if (kid == K_DMA_4 || kid == K_DMA_8) {
+        // 16-bit 4M, both operands chunked along k, whole tiles and k-tiles
+        if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
+        if (g.K % 32) return false;
+    }
     TileCfg t = tile_of(kid, dt, al);
-    // whole 16-byte chunks along every contiguous dimension, whole tiles along M and N
+    // whole 16-byte chunks along every chunked index (its low run starts at
+    // bit 0 and holds at least one chunk), whole tiles along M and N
     const int64_t q = dt == Dtype::C64 ? 2 : 4;
+    const int lq = dt == Dtype::C64 ? 1 : 2;
     if (g.K < q || g.K % q) return false;
-    if (!g.a_kc && g.M % q) return false;
-    if (!g.b_kc && g.N % q) return false;
+    auto chunked = [&](const Seg &sg, int64_t ext) { return sg.ls == 0 && seg_low_run(sg, ext) >= lq; };
+    if (!(g.a_kc ? chunked(g.ak, g.K) : chunked(g.am, g.M))) return false;
+    if (!(g.b_kc ? chunked(g.bk, g.K) : chunked(g.bn, g.N))) return false;
+    if (!(g.c_nc ? chunked(g.cn, g.N) : chunked(g.cm, g.M))) return false;
     if (dt != Dtype::C64 && g.K < 8) return false;
     if (g.M < t.BM || g.N < t.BN) return false;
     if (g.M % t.BM || g.N % t.BN) return false;
@@ -922,9 +1141,27 @@ static void launch_h_cfg(const void *A, const void *B, void *C, const GemmShape 
                        (uint32_t *)C, g, sc);
 }
 
+template <bool BF, int BM, int BN, int WM, int WN, int STAGES>
+static void launch_dma_cfg(const void *A, const void *B, void *C, const GemmShape &g, int S, const ScaleRefs &sc,
+                           hipStream_t st) {
+    using Tl = DTile<BM, BN, WM, WN, STAGES>;
+    auto kern = gemm_dma_h_kernel<BF, BM, BN, WM, WN, STAGES>;
+    static bool attr = false;
+    if (!attr) {
+        HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, Tl::LDS_BYTES));
+        attr = true;
+    }
+    int64_t tiles = (g.M / BM) * (g.N / BN);
+    dim3 grid((unsigned)tiles, (unsigned)(g.nb * g.split), S);
+    hipLaunchKernelGGL(kern, grid, dim3(Tl::NT), Tl::LDS_BYTES, st, (const uint32_t *)A, (const uint32_t *)B,
+                       (uint32_t *)C, g, sc);
+}
+
 template <bool BF>
 static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, const GemmShape &g, int S,
                      const ScaleRefs &sc, hipStream_t st) {
+    if (kid == K_DMA_4) return launch_dma_cfg<BF, 256, 128, 2, 2, 3>(A, B, C, g, S, sc, st);
+    if (kid == K_DMA_8) return launch_dma_cfg<BF, 256, 128, 4, 2, 3>(A, B, C, g, S, sc, st);
     if (al == Algo::M4) {
         switch (kid) {
             case K_MFMA_S: launch_h_cfg<BF, false, 64, 16, 32, 2, 1>(A, B, C, g, S, sc, st); break;

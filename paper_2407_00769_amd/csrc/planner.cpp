@@ -79,6 +79,62 @@ bool plan_tile_bits(const PermuteDesc &d, int lw, int nt_max, TileBits &tb) {
     return true;
 }
 
+static int ilog2_exact(int64_t v) {
+    int b = 0;
+    while (((int64_t)1 << b) < v) b++;
+    if (((int64_t)1 << b) != v) TNC_THROW(TNC_EINVAL, "internal: GEMM extent is not a power of two");
+    return b;
+}
+
+void set_plain_segs(GemmShape &g) {
+    const int lm = ilog2_exact(g.M), ln = ilog2_exact(g.N), lk = ilog2_exact(g.K);
+    g.am = g.a_kc ? Seg{62, lk, 0} : Seg{62, 0, 0};
+    g.ak = g.a_kc ? Seg{62, 0, 0} : Seg{62, lm, 0};
+    g.bn = g.b_kc ? Seg{62, lk, 0} : Seg{62, 0, 0};
+    g.bk = g.b_kc ? Seg{62, 0, 0} : Seg{62, ln, 0};
+    g.cm = g.c_nc ? Seg{62, ln, 0} : Seg{62, 0, 0};
+    g.cn = g.c_nc ? Seg{62, 0, 0} : Seg{62, lm, 0};
+}
+
+// Segment of the index whose labels are `idx` (most significant first) in a
+// tensor stored in `order` (most significant first); false if the labels are
+// not in at most two runs of consecutive bits in index order.
+bool derive_seg(const std::vector<int> &order, const std::vector<int> &idx, Seg &out) {
+    const int r = (int)order.size(), n = (int)idx.size();
+    out = Seg{};
+    if (n == 0) return true;
+    std::vector<int> bit(n);
+    for (int j = 0; j < n; j++) {   // index bit j (0 = least significant) -> memory bit
+        auto it = std::find(order.begin(), order.end(), idx[n - 1 - j]);
+        if (it == order.end()) return false;
+        bit[j] = r - 1 - (int)(it - order.begin());
+    }
+    int l = 1;
+    while (l < n && bit[l] == bit[0] + l) l++;
+    if (l == n) {
+        out = Seg{62, bit[0], 0};
+        return true;
+    }
+    for (int t = l + 1; t < n; t++)
+        if (bit[t] != bit[l] + (t - l)) return false;
+    out = Seg{l, bit[0], bit[l]};
+    return true;
+}
+
+GemmShape step_gemm(const StepRec &st) {
+    GemmShape g{st.M, st.N, st.K, st.nb, 0, 0, 0, st.M * st.K, st.N * st.K, st.M * st.N};
+    g.a_kc = st.a_kc;
+    g.b_kc = st.b_kc;
+    g.c_nc = st.c_nc;
+    g.am = st.am;
+    g.ak = st.ak;
+    g.bn = st.bn;
+    g.bk = st.bk;
+    g.cm = st.cm;
+    g.cn = st.cn;
+    return g;
+}
+
 // Does `order` read as [g0-block][g1-block][g2-block] (MSB first)?
 static bool has_pattern(const std::vector<int> &order, const std::vector<int> &grp /* label -> group */,
                         const std::vector<int> &sizes) {
@@ -101,7 +157,7 @@ static std::vector<int> extract(const std::vector<int> &order, const std::vector
 int choose_kernel(Dtype dt, Algo al, const GemmShape &g) {
     // largest matrix-core tile that divides the shape, once the step has
     // enough work for more than a handful of tiles; thin steps go to the VALU
-    static const int order[] = {K_MFMA_XL, K_MFMA_L2, K_MFMA_L, K_MFMA_M, K_MFMA_W, K_MFMA_S};
+    static const int order[] = {K_DMA_8, K_MFMA_XL, K_MFMA_L2, K_MFMA_L, K_MFMA_M, K_MFMA_W, K_MFMA_S};
     const double work = (double)g.M * (double)g.N * (double)g.K;
     if (work >= 1 << 18 && (g.N >= 16 || al == Algo::M3))
         for (int k : order)
@@ -256,17 +312,45 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         for (int l : st.k) grp[l] = 2;
         std::vector<int> sa = {(int)st.beta.size(), (int)st.m.size(), (int)st.k.size()};
         std::vector<int> sb = {(int)st.beta.size(), (int)st.n.size(), (int)st.k.size()};
-        // an operand fits as [batch][free][k] (K-contiguous) or [batch][k][free]
-        auto orient = [&](const TensorRec &T, const std::vector<int> &sz) -> int {
-            if (T.leaf) return -1;
-            if (has_pattern(T.labels, grp, sz)) return 1;
-            std::vector<int> g2(grp);
-            for (int l : T.labels) g2[l] = grp[l] == 1 ? 2 : (grp[l] == 2 ? 1 : grp[l]);
-            std::vector<int> sz2 = {sz[0], sz[2], sz[1]};
-            if (has_pattern(T.labels, g2, sz2)) return 0;
-            return -1;
+        // smallest run (bits) that a 16-byte chunk needs
+        const int lq = an.dt == Dtype::C64 ? 1 : 2;
+        // Can a stored order be read in place by a GEMM whose groups are `g`
+        // (0 batch, 1 free, 2 reduced)?  The batch labels must form the top
+        // block; below it the free and the reduced labels may each lie in at
+        // most two runs, and the lowest run must hold a whole chunk.  Returns
+        // the length of that lowest run (bits) and its group, or 0.
+        auto inplace = [&](const std::vector<int> &order, const std::vector<int> &g, int &low_group) -> int {
+            const int r = (int)order.size();
+            int pos = 0;
+            while (pos < r && g[order[pos]] == 0) pos++;
+            for (int t = pos; t < r; t++)
+                if (g[order[t]] == 0 || g[order[t]] < 0) return 0;
+            int runs[3] = {0, 0, 0};
+            int last = -1, low_len = 0;
+            for (int t = pos; t < r; t++) {
+                int v = g[order[t]];
+                if (v != last) {
+                    runs[v]++;
+                    low_len = 0;
+                }
+                low_len++;
+                last = v;
+            }
+            if (runs[1] > 2 || runs[2] > 2) return 0;
+            if (pos == r) {   // batch only: nothing to chunk
+                low_group = 2;
+                return 0;
+            }
+            low_group = last;
+            return low_len >= lq ? low_len : 0;
         };
-        int oa = orient(A, sa), ob = orient(B, sb);
+        auto orient = [&](const TensorRec &T) -> int {
+            if (T.leaf) return -1;
+            int lg = 0;
+            if (!inplace(T.labels, grp, lg)) return -1;
+            return lg == 2 ? 1 : 0;
+        };
+        int oa = orient(A), ob = orient(B);
         const double szA = std::ldexp(1.0, A.rank()), szB = std::ldexp(1.0, B.rank());
         // batch and k orders must agree between A and B; take them from a kept
         // operand, preferring the larger
@@ -291,11 +375,9 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             k_o = extract(src.labels, grp, 2);
         }
         std::vector<int> m_o = extract(A.labels, grp, 1), n_o = extract(B.labels, grp, 1);
-        // Z order: try both C orientations and both consumer orientations; free
-        // internal orders (operands that are permuted or gathered) follow the
-        // consumer's groups
-        // free orders follow the consumer's groups; within a group, labels summed
-        // later sit higher, so the stem keeps its soon-summed labels at the low end
+        // Result order.  Free orders of operands that are permuted or gathered
+        // follow the consumer's groups; within a group, labels summed later sit
+        // higher, so the stem keeps its soon-summed labels at the low end.
         auto ranked = [&](std::vector<int> v, bool kfirst) {
             std::stable_sort(v.begin(), v.end(), [&](int p, int q) {
                 auto key = [&](int l) { return cg[l] == 0 ? 0 : (kfirst ? (cg[l] == 2 ? 1 : 2) : cg[l]); };
@@ -304,57 +386,73 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             });
             return v;
         };
-        auto consumer_fits = [&](const std::vector<int> &zo) {
-            if (Z.consumer < 0) return true;
-            int last = -1;
-            bool inc = true, dec_ok = true;
-            // [0][1][2] or [0][2][1]
-            std::vector<int> key;
-            for (int l : zo) key.push_back(cg[l]);
-            for (int v : key) {
-                if (v < last) inc = false;
-                last = v;
+        // score of a result order: -1 if the consumer must permute it, else the
+        // shorter of the writer's and the reader's lowest runs (capped at 5
+        // bits: 128-byte runs coalesce fully), minus a small cost per split
+        std::vector<int> gw(L, -1);
+        auto score = [&](const std::vector<int> &zo, const std::vector<int> &mm, int nsplit) -> double {
+            for (int l : zo) gw[l] = 2;
+            for (int l : mm) gw[l] = 1;
+            for (int l : beta_o) gw[l] = 0;
+            int lgw = 0;
+            int wlow = inplace(zo, gw, lgw);
+            for (int l : zo) gw[l] = -1;
+            if (!wlow) return -1;
+            int rlow = 5;
+            if (Z.consumer >= 0) {
+                int lgr = 0;
+                rlow = inplace(zo, cg, lgr);
+                if (!rlow) return -1;
             }
-            last = -1;
-            for (int v : key) {
-                int w = v == 0 ? 0 : (v == 2 ? 1 : 2);
-                if (w < last) dec_ok = false;
-                last = w;
-            }
-            return inc || dec_ok;
+            return std::min({wlow, rlow, 5}) - 0.25 * nsplit;
         };
-        std::vector<int> best_m = m_o, best_n = n_o;
-        int best_cnc = 1;
-        bool found = false;
-        for (int kfirst = 0; kfirst < 2 && !found; kfirst++) {
-            std::vector<int> mm = keepA ? m_o : ranked(m_o, kfirst), nn = keepB ? n_o : ranked(n_o, kfirst);
-            for (int cnc = 1; cnc >= 0 && !found; cnc--) {
-                std::vector<int> zo = beta_o;
-                const auto &x = cnc ? mm : nn;
-                const auto &y = cnc ? nn : mm;
-                zo.insert(zo.end(), x.begin(), x.end());
-                zo.insert(zo.end(), y.begin(), y.end());
-                if (consumer_fits(zo)) {
-                    best_m = mm;
-                    best_n = nn;
-                    best_cnc = cnc;
-                    found = true;
-                }
-            }
-        }
-        if (!found) {
-            best_m = keepA ? m_o : ranked(m_o, false);
-            best_n = keepB ? n_o : ranked(n_o, false);
-        }
-        m_o = best_m;
-        n_o = best_n;
-        // operand orders
         auto cat3 = [](const std::vector<int> &a, const std::vector<int> &b, const std::vector<int> &c) {
             std::vector<int> r = a;
             r.insert(r.end(), b.begin(), b.end());
             r.insert(r.end(), c.begin(), c.end());
             return r;
         };
+        std::vector<int> best_m = keepA ? m_o : ranked(m_o, false), best_n = keepB ? n_o : ranked(n_o, false);
+        std::vector<int> best_z;
+        double best_s = -2;
+        for (int kfirst = 0; kfirst < 2; kfirst++) {
+            std::vector<int> mm = keepA ? m_o : ranked(m_o, kfirst), nn = keepB ? n_o : ranked(n_o, kfirst);
+            // plain [batch][X][Y] first; split layouts [batch][Xh][Yh][Xl][Yl]
+            // only if no plain order fits with runs of at least 4 entries
+            for (int pass = 0; pass < 2 && best_s < 2.5; pass++) {
+                for (int xm = 1; xm >= 0; xm--) {
+                    const auto &X = xm ? mm : nn;
+                    const auto &Y = xm ? nn : mm;
+                    const int nx = (int)X.size(), ny = (int)Y.size();
+                    for (int sx = pass ? 0 : nx; sx <= nx; sx++)
+                        for (int sy = pass ? 0 : ny; sy <= ny; sy++) {
+                            int nsplit = (sx > 0 && sx < nx) + (sy > 0 && sy < ny);
+                            if (pass && !nsplit) continue;
+                            std::vector<int> zo = beta_o;
+                            zo.insert(zo.end(), X.begin(), X.begin() + sx);
+                            zo.insert(zo.end(), Y.begin(), Y.begin() + sy);
+                            zo.insert(zo.end(), X.begin() + sx, X.end());
+                            zo.insert(zo.end(), Y.begin() + sy, Y.end());
+                            double sc = score(zo, mm, nsplit);
+                            if (sc > best_s) {
+                                best_s = sc;
+                                best_z = zo;
+                                best_m = mm;
+                                best_n = nn;
+                            }
+                        }
+                }
+            }
+            if (best_s >= 0) break;
+        }
+        if (best_s < 0) {   // nothing fits the consumer: plain order, the consumer permutes
+            best_z = cat3(beta_o, best_m, best_n);
+            std::vector<int> zt = cat3(beta_o, best_n, best_m);
+            if (score(best_z, best_m, 0) < 0 && score(zt, best_m, 0) >= 0) best_z = zt;
+        }
+        m_o = best_m;
+        n_o = best_n;
+        // operand orders
         if (keepA) {
             st.a_kc = oa;
         } else {
@@ -377,12 +475,16 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             B.labels = want;
             st.b_kc = 1;
         }
-        st.c_nc = best_cnc;
         st.beta = beta_o;
         st.m = m_o;
         st.n = n_o;
         st.k = k_o;
-        Z.labels = st.c_nc ? cat3(beta_o, m_o, n_o) : cat3(beta_o, n_o, m_o);
+        Z.labels = best_z;
+        {
+            // the result is written in chunks along the index of its lowest label
+            int low = Z.labels.empty() ? -1 : Z.labels.back();
+            st.c_nc = (low >= 0 && std::find(m_o.begin(), m_o.end(), low) != m_o.end()) ? 0 : 1;
+        }
         st.nb = (int64_t)1 << st.beta.size();
         st.M = (int64_t)1 << st.m.size();
         st.N = (int64_t)1 << st.n.size();
@@ -392,11 +494,11 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         st.perm_bytes = (st.perm_a ? 2.0 * es * szA : 0.0) + (st.perm_b ? 2.0 * es * szB : 0.0);
         st.hoist_a = st.perm_a && st.dep && !A.dep;
         st.hoist_b = st.perm_b && st.dep && !B.dep;
-        GemmShape g{st.M, st.N, st.K, st.nb, 0, 0, 0, st.M * st.K, st.N * st.K, st.M * st.N};
-        g.a_kc = st.a_kc;
-        g.b_kc = st.b_kc;
-        g.c_nc = st.c_nc;
-        st.kernel = choose_kernel(an.dt, an.al, g);
+        if (!derive_seg(A.labels, st.m, st.am) || !derive_seg(A.labels, st.k, st.ak) ||
+            !derive_seg(B.labels, st.n, st.bn) || !derive_seg(B.labels, st.k, st.bk) ||
+            !derive_seg(Z.labels, st.m, st.cm) || !derive_seg(Z.labels, st.n, st.cn))
+            TNC_THROW(TNC_EINVAL, "internal: operand layout has more than two runs per index");
+        st.kernel = choose_kernel(an.dt, an.al, step_gemm(st));
         for (int l : st.beta) grp[l] = -1;
         for (int l : st.m) grp[l] = -1;
         for (int l : st.n) grp[l] = -1;

@@ -28,7 +28,8 @@ struct StepRec {
     int64_t scr_a = -1, scr_b = -1;   // arena offsets of the permuted operands
     std::vector<int> a_from, b_from;  // operand orders before the permute
     int64_t M = 1, N = 1, K = 1, nb = 1;
-    int a_kc = 1, b_kc = 1, c_nc = 1;  // operand / result orientation (see GemmShape)
+    int a_kc = 1, b_kc = 1, c_nc = 1;  // operand / result chunk direction (see GemmShape)
+    Seg am, ak, bn, bk, cm, cn;        // where each GEMM index lives in A, B and the result
     bool hoist_a = false, hoist_b = false;   // permute of an invariant operand, done once per call
     bool dep = false;
     int kernel = K_NAIVE;
@@ -57,6 +58,13 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
 // Byte offsets of every tensor and scratch buffer for S slices in flight;
 // returns the arena peak in bytes.
 int64_t plan_memory(Analysis &an, int S, bool assign);
+
+// Segment of the GEMM index whose labels are `idx` (most significant first)
+// in a tensor stored in `order`; false if they are not in at most two runs.
+bool derive_seg(const std::vector<int> &order, const std::vector<int> &idx, Seg &out);
+
+// GEMM descriptor of a step (slice strides zero).
+GemmShape step_gemm(const StepRec &st);
 
 // Default kernel choice for a step shape.
 int choose_kernel(Dtype dt, Algo al, const GemmShape &g);

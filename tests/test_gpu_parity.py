@@ -102,10 +102,12 @@ def _check_contract(T, ctx, prec, nb, m, n, k, seed, scale_log2=0):
 
 
 KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5, "mfma_xl": 6,
-           "mfma_l2": 7}
+           "mfma_l2": 7, "dma_4": 8, "dma_8": 9}
 SHAPES = [  # nb, m, n, k  (log2)
     (0, 9, 6, 5), (1, 8, 5, 3), (0, 10, 4, 6), (2, 7, 7, 4), (0, 8, 0, 2), (0, 6, 3, 0), (0, 12, 5, 7),
     (0, 9, 8, 6), (1, 8, 7, 5),
+    (0, 9, 8, 9),   # few tiles, long k: split-K partial sums
+    (1, 8, 7, 6),   # one 256 x 128 tile per batch entry
 ]
 
 
@@ -131,7 +133,7 @@ def _oriented_case(rng, m, n, k, a_kc, b_kc, c_nc):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("kname", ["skinny", "mfma_s", "mfma_l", "mfma_xl", "mfma_l2", "mfma_w"])
+@pytest.mark.parametrize("kname", ["skinny", "mfma_s", "mfma_l", "mfma_xl", "mfma_l2", "mfma_w", "dma_4"])
 def test_contract_orientations(T, ctx, prec, kname, monkeypatch):
     # every combination of A [m][k] / [k][m], B [n][k] / [k][n], C [m][n] / [n][m]
     # runs without a permute and matches the oracle
@@ -155,6 +157,38 @@ def test_contract_orientations(T, ctx, prec, kname, monkeypatch):
                     bound = bound + 6 * U[prec] * np.abs(mag)
                 err = np.abs(got - ref)
                 assert np.all(err <= bound), (prec, kname, a_kc, b_kc, c_nc, float(np.max(err / bound)))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kname", ["skinny", "mfma_m", "mfma_xl", "mfma_l2", "dma_4", "dma_8"])
+def test_contract_split_layouts(T, ctx, prec, kname, monkeypatch):
+    # operands and result whose GEMM indices lie in two runs each (A as
+    # [m_hi][k_hi][m_lo][k_lo], B as [k_hi][n][k_lo], C as [m_hi][n_hi][m_lo][n_lo])
+    # are used in place, with no permute, and match the oracle
+    monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
+    rng = np.random.default_rng(12)
+    m, n, k = 9, 8, 6
+    ml = list(range(0, m))
+    nl = list(range(m, m + n))
+    kl = list(range(m + n, m + n + k))
+    al = ml[:4] + kl[:3] + ml[4:] + kl[3:]
+    bl = kl[:3] + nl + kl[3:]
+    cl = ml[:5] + nl[:3] + ml[5:] + nl[3:]
+    a = (rng.normal(size=2 ** len(al)) + 1j * rng.normal(size=2 ** len(al))) / np.sqrt(2 * 2 ** k)
+    b = (rng.normal(size=2 ** len(bl)) + 1j * rng.normal(size=2 ** len(bl))) / np.sqrt(2)
+    A, av = to_storage(a, prec)
+    B, bv = to_storage(b, prec)
+    C = empty_storage((2 ** len(cl),), prec)
+    times, _ = T.tnc_contract(ctx, prec, A, al, B, bl, C, cl)
+    assert times[0] < 0.05 and times[1] < 0.05 and times[3] < 0.05   # no permute ran (ms)
+    got = from_storage(C, prec).reshape((2,) * len(cl))
+    ref = pairwise.contract_pair(av.reshape((2,) * len(al)), al, bv.reshape((2,) * len(bl)), bl, cl)
+    mag = pairwise.contract_pair(np.abs(av).reshape((2,) * len(al)), al, np.abs(bv).reshape((2,) * len(bl)), bl, cl)
+    bound = 4 * 64 * 2.0 ** -24 * np.abs(mag) + U[prec] * np.abs(ref) * 1.01 + 1e-30
+    if prec.endswith("3m"):
+        bound = bound + 6 * U[prec] * np.abs(mag)
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), (prec, kname, float(np.max(err / bound)))
 
 
 @pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m", "f16_3m"])
