@@ -221,6 +221,178 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(const W *__restrict__ 
     finish_max<SCALE>(sc, s, mx);
 }
 
+// ===================================================================== thin: N <= 16, K <= 64 (VALU)
+// HBM-bound steps (a wide operand times a few columns).  B's NN columns are
+// staged in LDS once per block; the grid is capped and threads stride over
+// row units.  A unit is one row whose k entries are read in 16-byte loads
+// (MODE 0, A chunked along k) or V consecutive rows read with one 16-byte
+// load per k (MODE 1, A chunked along m).  Results leave in 16-byte stores
+// when the result is chunked along the index the unit spans.
+
+template <typename W> struct alignas(16) Pack16 {
+    static constexpr int N = 16 / sizeof(W);
+    W w[N];
+};
+
+template <typename W, bool SCALE>
+__device__ __forceinline__ W make_entry(float re, float im, float scale, float &mx) {
+    if (SCALE) {
+        re *= scale;
+        im *= scale;
+    }
+    W w = Pack<W>::make(re, im);
+    if (SCALE) {
+        float2 f = unpack(w);
+        mx = fmaxf(mx, absmax_nan(f.x, f.y));
+    }
+    return w;
+}
+
+template <typename W, int NN, int MODE, bool SCALE, bool M3>
+__global__ void __launch_bounds__(256) gemm_thin_kernel(const W *__restrict__ A, const W *__restrict__ B,
+                                                        W *__restrict__ C, GemmShape g, ScaleRefs sc) {
+    constexpr int V = 16 / sizeof(W);
+    constexpr int KMAX = 64;
+    constexpr int R = MODE == 1 ? V : 1;   // rows per unit
+    __shared__ float2 Bs[NN][KMAX];
+    __shared__ float Bsum[M3 ? NN : 1][KMAX];
+    const int s = blockIdx.z;
+    const int64_t nchunks = g.N / NN;
+    const int64_t b = blockIdx.y / nchunks;
+    const int64_t n0 = (blockIdx.y - b * nchunks) * NN;
+    int shift = SCALE ? step_shift(sc, s) : 0;
+    if (SCALE && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
+    const float scale = pow2_neg(shift);
+    const W *Ap = A + s * g.sA + b * g.bA;
+    const W *Bp = B + s * g.sB + b * g.bB;
+    W *Cp = C + s * g.sC + b * g.bC;
+    const int K = (int)g.K;
+    for (int e = threadIdx.x; e < NN * KMAX; e += blockDim.x) {
+        const int j = e / KMAX, kk = e - j * KMAX;
+        float2 v = make_float2(0.f, 0.f);
+        if (kk < K) v = unpack(Bp[b_index(g, n0 + j, kk)]);
+        Bs[j][kk] = v;
+        if constexpr (M3) Bsum[j][kk] = round_to_storage<W>(v.x + v.y);
+    }
+    __syncthreads();
+    // vector stores: C chunked along the unit's span
+    const bool vstore = MODE == 0 ? (g.c_nc && NN % V == 0) : (!g.c_nc);
+    const int64_t units = g.M / R;
+    float mx = 0.f;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < units; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = u * R;
+        float2 acc[R][NN];
+        float t3[M3 ? R : 1][M3 ? NN : 1];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int j = 0; j < NN; j++) {
+                acc[r][j] = make_float2(0.f, 0.f);
+                if constexpr (M3) t3[r][j] = 0.f;
+            }
+        const W *ap = Ap + seg_offset(g.am, m);
+        auto madd = [&](int r, float2 a, int k) {
+            if constexpr (!M3) {
+#pragma unroll
+                for (int j = 0; j < NN; j++) {
+                    float2 bb = Bs[j][k];
+                    acc[r][j].x = fmaf(a.x, bb.x, acc[r][j].x);
+                    acc[r][j].x = fmaf(-a.y, bb.y, acc[r][j].x);
+                    acc[r][j].y = fmaf(a.x, bb.y, acc[r][j].y);
+                    acc[r][j].y = fmaf(a.y, bb.x, acc[r][j].y);
+                }
+            } else {
+                float as = round_to_storage<W>(a.x + a.y);
+#pragma unroll
+                for (int j = 0; j < NN; j++) {
+                    float2 bb = Bs[j][k];
+                    acc[r][j].x = fmaf(a.x, bb.x, acc[r][j].x);   // T1
+                    acc[r][j].y = fmaf(a.y, bb.y, acc[r][j].y);   // T2
+                    t3[r][j] = fmaf(as, Bsum[j][k], t3[r][j]);    // T3
+                }
+            }
+        };
+        if constexpr (MODE == 0) {
+            for (int k0 = 0; k0 < K; k0 += V) {
+                Pack16<W> v = *(const Pack16<W> *)(ap + seg_offset(g.ak, k0));
+#pragma unroll
+                for (int q = 0; q < V; q++) madd(0, unpack(v.w[q]), k0 + q);
+            }
+        } else {
+            for (int k = 0; k < K; k++) {
+                Pack16<W> v = *(const Pack16<W> *)(ap + seg_offset(g.ak, k));
+#pragma unroll
+                for (int q = 0; q < V; q++) madd(q, unpack(v.w[q]), k);
+            }
+        }
+        auto value = [&](int r, int j, float &re, float &im) {
+            if constexpr (!M3) {
+                re = acc[r][j].x;
+                im = acc[r][j].y;
+            } else {
+                re = acc[r][j].x - acc[r][j].y;
+                im = t3[r][j] - acc[r][j].x - acc[r][j].y;
+            }
+        };
+        if (vstore) {
+            if constexpr (MODE == 0) {
+#pragma unroll
+                for (int j0 = 0; j0 < NN; j0 += V) {
+                    Pack16<W> o;
+#pragma unroll
+                    for (int q = 0; q < V; q++) {
+                        float re, im;
+                        value(0, (j0 + q) % NN, re, im);
+                        o.w[q] = make_entry<W, SCALE>(re, im, scale, mx);
+                    }
+                    *(Pack16<W> *)(Cp + c_index(g, m, n0 + j0)) = o;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NN; j++) {
+                    Pack16<W> o;
+#pragma unroll
+                    for (int q = 0; q < V; q++) {
+                        float re, im;
+                        value(q % R, j, re, im);
+                        o.w[q] = make_entry<W, SCALE>(re, im, scale, mx);
+                    }
+                    *(Pack16<W> *)(Cp + c_index(g, m, n0 + j)) = o;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int j = 0; j < NN; j++) {
+                    float re, im;
+                    value(r, j, re, im);
+                    Cp[c_index(g, m + r, n0 + j)] = make_entry<W, SCALE>(re, im, scale, mx);
+                }
+        }
+    }
+    finish_max<SCALE>(sc, s, mx);
+}
+
+// Which thin variant can run a shape (-1: none).
+static int thin_mode(Dtype dt, const GemmShape &g) {
+    const int lv = dt == Dtype::C64 ? 1 : 2;   // log2 of the entries in 16 bytes
+    const int64_t v = (int64_t)1 << lv;
+    if (g.K > 64 || g.N > 16 || g.nb * (g.N / std::min<int64_t>(g.N, 16)) > 65535) return -1;
+    auto ok = [&](const Seg &sg, int64_t ext) { return sg.ls == 0 && seg_low_run(sg, ext) >= lv && ext % v == 0; };
+    bool c_ok;
+    if (g.a_kc && ok(g.ak, g.K)) {
+        // vector stores need C chunked along n with whole chunks
+        c_ok = !g.c_nc || std::min<int64_t>(g.N, 16) % v != 0 || ok(g.cn, g.N);
+        return c_ok ? 0 : -1;
+    }
+    if (!g.a_kc && ok(g.am, g.M)) {
+        c_ok = g.c_nc || ok(g.cm, g.M);
+        return c_ok ? 1 : -1;
+    }
+    return -1;
+}
+
 // ===================================================================== matrix cores, 16-bit
 //
 // Block tile BM rows x BN complex columns, k-tile BK complex; WM x WN waves.
@@ -1105,6 +1277,39 @@ static void launch_valu(int kid, Algo al, const void *A, const void *B, void *C,
     }
     int64_t nn = g.N < 16 ? g.N : 16;
     int64_t nch = (g.N + nn - 1) / nn;
+    const Dtype dt = sizeof(W) == 8 ? Dtype::C64 : Dtype::F16;
+    const int mode = thin_mode(dt, g);
+    if (mode >= 0) {
+        const int64_t units = mode == 0 ? g.M : g.M / (16 / (int64_t)sizeof(W));
+        dim3 tg((unsigned)std::min<int64_t>((units + 255) / 256, 2048), (unsigned)(g.nb * nch), S);
+#define THIN(NNV)                                                                                          \
+    do {                                                                                                   \
+        if (mode == 0) {                                                                                   \
+            if (al == Algo::M3)                                                                            \
+                hipLaunchKernelGGL((gemm_thin_kernel<W, NNV, 0, SCALE, true>), tg, dim3(256), 0, st,       \
+                                   (const W *)A, (const W *)B, (W *)C, g, sc);                             \
+            else                                                                                           \
+                hipLaunchKernelGGL((gemm_thin_kernel<W, NNV, 0, SCALE, false>), tg, dim3(256), 0, st,      \
+                                   (const W *)A, (const W *)B, (W *)C, g, sc);                             \
+        } else {                                                                                           \
+            if (al == Algo::M3)                                                                            \
+                hipLaunchKernelGGL((gemm_thin_kernel<W, NNV, 1, SCALE, true>), tg, dim3(256), 0, st,       \
+                                   (const W *)A, (const W *)B, (W *)C, g, sc);                             \
+            else                                                                                           \
+                hipLaunchKernelGGL((gemm_thin_kernel<W, NNV, 1, SCALE, false>), tg, dim3(256), 0, st,      \
+                                   (const W *)A, (const W *)B, (W *)C, g, sc);                             \
+        }                                                                                                  \
+    } while (0)
+        switch (nn) {
+            case 1: THIN(1); break;
+            case 2: THIN(2); break;
+            case 4: THIN(4); break;
+            case 8: THIN(8); break;
+            default: THIN(16); break;
+        }
+#undef THIN
+        return;
+    }
     dim3 grid((unsigned)((g.M + 255) / 256), (unsigned)(g.nb * nch), S);
 #define SKINNY(NNV)                                                                                        \
     do {                                                                                                   \
