@@ -130,8 +130,9 @@ enum KernelId : int {
     K_MFMA_XL = 6,    // large tiles for compute-bound steps
     K_MFMA_L2 = 7,
     K_DMA_4 = 8,      // 16-bit 4M, operands streamed into LDS by DMA; 4 waves
-    K_DMA_8 = 9,      // the same with 8 waves
-    K_COUNT = 10
+    K_DMA_8 = 9,      // the same with 8 waves (4 x 2)
+    K_DMA_8W = 10,    // 8 waves as 2 x 4 (wider wave tiles along n)
+    K_COUNT = 11
 };
 const char *kernel_name(int k);
 // Segments of the plain layouts ([m][k] or [k][m] etc., as the chunk flags

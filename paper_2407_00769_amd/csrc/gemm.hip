@@ -748,11 +748,18 @@ __global__ void __launch_bounds__(64 * WM * WN)
 // matrix cores work on the oldest.  An LDS row is one operand row's 32
 // complex k (128 bytes, 8 chunks); chunk q of row r sits in slot q ^ (r & 7),
 // so the DMA (whole rows) and the fragment reads (8 rows, one chunk each) are
-// both free of bank conflicts.  Fragments and the 4M padding of B are as in
-// gemm_mfma_h_kernel.
+// both free of bank conflicts.
+//
+// 4M here keeps the real and the imaginary parts of C in separate
+// accumulators: a B fragment is 32 complex columns (lane l: column l % 32,
+// complex k 4(l/32)..+3), read once, and gives the real-part operand
+// (br, -bi) by one XOR and the imaginary-part operand (bi, br) by one byte
+// permute per register:
+//     Re C = sum_k' A'[m][k'] (br, -bi)[k'],   Im C = sum_k' A'[m][k'] (bi, br)[k']
+// with A' the interleaved (re, im) view of A (k' = 2k + c).
 
-// s_waitcnt vmcnt(VM) lgkmcnt(0), expcnt untouched (gfx9 field layout), as a
-// compiler barrier for memory too
+// s_waitcnt vmcnt(VM) lgkmcnt(0), expcnt untouched (gfx9 field layout), then
+// s_barrier; a compiler barrier for memory on both sides
 template <int VM> __device__ __forceinline__ void ring_wait() {
     static_assert(VM >= 0 && VM < 64, "vmcnt");
     asm volatile("" ::: "memory");
@@ -770,12 +777,12 @@ struct DTile {
     static constexpr int RING_BYTES = STAGES * STAGE_BYTES;
     static constexpr int C_BYTES = BM * BN * 4;
     static constexpr int LDS_BYTES = RING_BYTES > C_BYTES ? RING_BYTES : C_BYTES;
-    static constexpr int WTM = BM / WM, WTN = 2 * BN / WN;       // rows, real columns per wave
-    static constexpr int FM = WTM / 32, FN = WTN / 32;
+    static constexpr int WTM = BM / WM, WTC = BN / WN;          // rows, complex columns per wave
+    static constexpr int FM = WTM / 32, FC = WTC / 32;
     static constexpr int A_PER = BM / 8 / (NT / 64);             // 1 KB DMA blocks per wave and stage
     static constexpr int B_PER = BN / 8 / (NT / 64);
     static constexpr int LPT = A_PER + B_PER;                    // DMA loads per thread and stage
-    static_assert(FM >= 1 && FN >= 1, "wave tile too small");
+    static_assert(FM >= 1 && FC >= 1, "wave tile too small");
     static_assert(A_PER >= 1 && B_PER >= 1 && A_PER * (NT / 64) * 8 == BM && B_PER * (NT / 64) * 8 == BN, "DMA split");
     static_assert(STAGES >= 2 && LPT * (STAGES - 2) < 64, "stages");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
@@ -797,7 +804,7 @@ __global__ void __launch_bounds__(64 * WM * WN)
                       GemmShape g, ScaleRefs sc) {
     using Tl = DTile<BM, BN, WM, WN, STAGES>;
     using W = typename std::conditional<BF, Bf16Word, HalfWord>::type;
-    constexpr int NT = Tl::NT, FM = Tl::FM, FN = Tl::FN, WTM = Tl::WTM, WTN = Tl::WTN, BK = Tl::BK;
+    constexpr int NT = Tl::NT, FM = Tl::FM, FC = Tl::FC, WTM = Tl::WTM, WTC = Tl::WTC, BK = Tl::BK;
     extern __shared__ __align__(16) uint8_t smem[];
 
     const int s = blockIdx.z;
@@ -815,106 +822,154 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const uint32_t *Ap = A + s * g.sA + b * g.bA;
     const uint32_t *Bp = B + s * g.sB + b * g.bB;
     uint32_t *Cp = C + s * g.sC + b * g.bC;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WN, wn = wave % WN;
 
     // DMA: wave w fills 1 KB blocks w, w + NT/64, ... of each operand; lane j
     // of a block writes row 8 * block + j / 8, slot j % 8, which holds chunk
-    // q = (j % 8) ^ (j / 8) of that row
+    // q = (j % 8) ^ (j / 8) of that row.  For k0 a multiple of 32,
+    // offset(k0 + 4q) = offset(k0) + offset(4q) (both runs of a Seg are at
+    // least as aligned), so the lane part is folded into the row pointers and
+    // each stage adds one uniform offset.
     const int dq = (lane & 7) ^ (lane >> 3);
-    int64_t arow[Tl::A_PER], brow[Tl::B_PER];
+    const uint32_t *pa[Tl::A_PER], *pb[Tl::B_PER];
 #pragma unroll
-    for (int i = 0; i < Tl::A_PER; i++) arow[i] = seg_offset(g.am, m0 + 8 * (wave + i * (NT / 64)) + (lane >> 3));
+    for (int i = 0; i < Tl::A_PER; i++)
+        pa[i] = Ap + seg_offset(g.am, m0 + 8 * (wave + i * (NT / 64)) + (lane >> 3)) + seg_offset(g.ak, 4 * dq);
 #pragma unroll
-    for (int i = 0; i < Tl::B_PER; i++) brow[i] = seg_offset(g.bn, n0 + 8 * (wave + i * (NT / 64)) + (lane >> 3));
-    const int64_t nk_all = g.K / BK;
-    const int64_t kt0 = nk_all * part / P, kt1 = nk_all * (part + 1) / P;
-    const int64_t nk = kt1 - kt0;
-    auto issue = [&](int64_t kt) {
+    for (int i = 0; i < Tl::B_PER; i++)
+        pb[i] = Bp + seg_offset(g.bn, n0 + 8 * (wave + i * (NT / 64)) + (lane >> 3)) + seg_offset(g.bk, 4 * dq);
+    const int nk_all = (int)(g.K / BK);
+    const int kt0 = (int)(nk_all * part / P), kt1 = (int)(nk_all * (part + 1) / P);
+    const int nk = kt1 - kt0;
+    auto issue = [&](int kt) {
         uint8_t *base = smem + (kt % STAGES) * Tl::STAGE_BYTES;
-        const int64_t k = (kt0 + kt) * BK + 4 * dq;
-        const int64_t ka = seg_offset(g.ak, k), kb = seg_offset(g.bk, k);
+        const int64_t k0 = (int64_t)(kt0 + kt) * BK;
+        const int64_t ka = seg_offset(g.ak, k0), kb = seg_offset(g.bk, k0);
 #pragma unroll
         for (int i = 0; i < Tl::A_PER; i++)
-            __builtin_amdgcn_global_load_lds((const void *)(Ap + arow[i] + ka),
+            __builtin_amdgcn_global_load_lds((const void *)(pa[i] + ka),
                                              (__attribute__((address_space(3))) void *)(base + (wave + i * (NT / 64)) * 1024),
                                              16, 0, 0);
 #pragma unroll
         for (int i = 0; i < Tl::B_PER; i++)
-            __builtin_amdgcn_global_load_lds((const void *)(Bp + brow[i] + kb),
+            __builtin_amdgcn_global_load_lds((const void *)(pb[i] + kb),
                                              (__attribute__((address_space(3))) void *)(base + Tl::A_BYTES +
                                                                                         (wave + i * (NT / 64)) * 1024),
                                              16, 0, 0);
     };
 
-    floatx16 acc[FM][FN];
+    floatx16 acc[FM][FC][2];
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
-        for (int j = 0; j < FN; j++)
+        for (int j = 0; j < FC; j++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+            for (int r = 0; r < 16; r++) acc[i][j][0][r] = acc[i][j][1][r] = 0.f;
 
-    // fragment addresses: A row wm*WTM + 32i + lane%32 (row & 7 = lane & 7);
-    // B complex row (wn*WTN + 32j + lane%32) / 2 (row & 7 = (lane >> 1) & 7)
-    const int a_s0 = (lane >> 5) ^ (lane & 7), b_s0 = (lane >> 5) ^ ((lane >> 1) & 7);
-    const int a_row0 = (wm * WTM + (lane & 31)) * 128;
-    const int b_row0 = ((wn * WTN + (lane & 31)) >> 1) * 128;
-    const Pad4M pad(lane & 1);
+    // fragment rows: wm*WTM + 32i + lane%32 (A) and wn*WTC + 32j + lane%32
+    // (B); both have row & 7 = lane & 7, so the slot of chunk 2kk + lane/32
+    // is (2kk) ^ (lane/32) ^ (lane & 7); offsets within a stage, per kk
+    const int f_s0 = (lane >> 5) ^ (lane & 7);
+    int a_off[BK / 8], b_off[BK / 8];
+#pragma unroll
+    for (int kk = 0; kk < BK / 8; kk++) {
+        a_off[kk] = (wm * WTM + (lane & 31)) * 128 + ((kk << 1) ^ f_s0) * 16;
+        b_off[kk] = Tl::A_BYTES + (wn * WTC + (lane & 31)) * 128 + ((kk << 1) ^ f_s0) * 16;
+    }
+
+    auto load = [&](const uint8_t *sb, int kk, u32x4 (&fa)[FM], u32x4 (&fb)[FC]) {
+#pragma unroll
+        for (int i = 0; i < FM; i++) fa[i] = *(const u32x4 *)(sb + a_off[kk] + i * 32 * 128);
+#pragma unroll
+        for (int j = 0; j < FC; j++) fb[j] = *(const u32x4 *)(sb + b_off[kk] + j * 32 * 128);
+    };
+    // B fragment -> real-part operand (br, -bi) and imaginary-part operand (bi, br)
+    auto xform = [&](const u32x4 (&fb)[FC], u32x4 (&bre)[FC], u32x4 (&bim)[FC]) {
+#pragma unroll
+        for (int j = 0; j < FC; j++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                bre[j][q] = fb[j][q] ^ 0x80000000u;
+                bim[j][q] = __builtin_amdgcn_perm(fb[j][q], fb[j][q], 0x01000302u);
+            }
+    };
+    auto madd = [&](const u32x4 (&fa)[FM], const u32x4 (&bre)[FC], const u32x4 (&bim)[FC]) {
+#pragma unroll
+        for (int j = 0; j < FC; j++)
+#pragma unroll
+            for (int i = 0; i < FM; i++) {
+                acc[i][j][0] = mfma16<BF>(fa[i], bre[j], acc[i][j][0]);
+                acc[i][j][1] = mfma16<BF>(fa[i], bim[j], acc[i][j][1]);
+            }
+    };
+    static_assert(BK / 8 == 4, "the k-step pipeline below is written for four steps per stage");
 
 #pragma unroll
     for (int st = 0; st < STAGES - 1; st++)
         if (st < nk) issue(st);
-    for (int64_t kt = 0; kt < nk; kt++) {
+    for (int kt = 0; kt < nk; kt++) {
         ring_wait_for<STAGES - 2, Tl::LPT>(nk - 1 - kt);
         if (kt + STAGES - 1 < nk) issue(kt + STAGES - 1);
-        const uint8_t *ab = smem + (kt % STAGES) * Tl::STAGE_BYTES;
-        const uint8_t *bb = ab + Tl::A_BYTES;
-#pragma unroll
-        for (int kk = 0; kk < BK / 8; kk++) {
-            u32x4 af[FM], bf[FN];
-            const int as = ((kk << 1) ^ a_s0) * 16, bs = ((kk << 1) ^ b_s0) * 16;
-#pragma unroll
-            for (int i = 0; i < FM; i++) af[i] = *(const u32x4 *)(ab + a_row0 + i * 32 * 128 + as);
-#pragma unroll
-            for (int j = 0; j < FN; j++) bf[j] = pad(*(const u32x4 *)(bb + b_row0 + j * 16 * 128 + bs));
-#pragma unroll
-            for (int i = 0; i < FM; i++)
-#pragma unroll
-                for (int j = 0; j < FN; j++) acc[i][j] = mfma16<BF>(af[i], bf[j], acc[i][j]);
-        }
+        const uint8_t *sb = smem + (kt % STAGES) * Tl::STAGE_BYTES;
+        // Two register sets of fragments: the reads of step kk+1 are issued
+        // before the matrix-core work of step kk, and a set's first use (its
+        // B transform) comes before the next reads, so each wait covers only
+        // reads that had a whole step to land.  The scheduling barriers keep
+        // the compiler from undoing that order.
+        u32x4 fa0[FM], fb0[FC], re0[FC], im0[FC], fa1[FM], fb1[FC], re1[FC], im1[FC];
+        load(sb, 0, fa0, fb0);
+        xform(fb0, re0, im0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(sb, 1, fa1, fb1);
+        __builtin_amdgcn_sched_barrier(0);
+        madd(fa0, re0, im0);
+        __builtin_amdgcn_sched_barrier(0);
+        xform(fb1, re1, im1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(sb, 2, fa0, fb0);
+        __builtin_amdgcn_sched_barrier(0);
+        madd(fa1, re1, im1);
+        __builtin_amdgcn_sched_barrier(0);
+        xform(fb0, re0, im0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(sb, 3, fa1, fb1);
+        __builtin_amdgcn_sched_barrier(0);
+        madd(fa0, re0, im0);
+        __builtin_amdgcn_sched_barrier(0);
+        xform(fb1, re1, im1);
+        madd(fa1, re1, im1);
     }
     ring_wait<0>();   // every wave is done with the ring before it is reused
 
     if (P > 1) {
-        float *pp = (float *)(g.part + ((s * g.nb + b) * P + part) * g.M * g.N);
+        float2 *pp = g.part + ((s * g.nb + b) * P + part) * g.M * g.N;
 #pragma unroll
         for (int i = 0; i < FM; i++)
 #pragma unroll
-            for (int j = 0; j < FN; j++)
+            for (int j = 0; j < FC; j++)
 #pragma unroll
                 for (int r = 0; r < 16; r++) {
                     int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    int col = wn * WTN + j * 32 + (lane & 31);
-                    pp[(m0 + row) * 2 * g.N + 2 * n0 + col] = acc[i][j][r];
+                    int col = wn * WTC + j * 32 + (lane & 31);
+                    pp[(m0 + row) * g.N + n0 + col] = make_float2(acc[i][j][0][r], acc[i][j][1][r]);
                 }
         return;
     }
     // epilogue: scale, round, stage the tile as complex words [BM][BN], write out
-    uint16_t *Ch = (uint16_t *)smem;
+    uint32_t *Cw = (uint32_t *)smem;
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
-        for (int j = 0; j < FN; j++)
+        for (int j = 0; j < FC; j++)
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                int col = wn * WTN + j * 32 + (lane & 31);
-                float v = acc[i][j][r] * scale;
-                Ch[row * (2 * BN) + col] = (uint16_t)(BF ? f2bf_bits(v) : f2h_bits(v));
+                int col = wn * WTC + j * 32 + (lane & 31);
+                Cw[row * BN + col] = Pack<W>::make(acc[i][j][0][r] * scale, acc[i][j][1][r] * scale).w;
             }
     __syncthreads();
-    const uint32_t *Cw = (const uint32_t *)smem;
     float mx = 0.f;
     constexpr int C_CHUNKS = BM * BN / 4;
     for (int c = tid; c < C_CHUNKS; c += NT) {
@@ -1187,6 +1242,7 @@ const char *kernel_name(int k) {
         case K_MFMA_L2: return "mfma_l2";
         case K_DMA_4: return "dma_4";
         case K_DMA_8: return "dma_8";
+        case K_DMA_8W: return "dma_8w";
         default: return "?";
     }
 }
@@ -1215,6 +1271,7 @@ static TileCfg tile_of(int kid, Dtype dt, Algo al) {
             case K_MFMA_L2: return {128, 128};
             case K_DMA_4: return {256, 128};
             case K_DMA_8: return {256, 128};
+            case K_DMA_8W: return {256, 128};
         }
     } else {
         switch (kid) {
@@ -1239,7 +1296,7 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
     if (g.nb > 65535) return false;
     if (kid < 0 || kid >= K_COUNT) return false;
     if (dt == Dtype::C64 && al == Algo::M3) return false;
-    if (kid == K_DMA_4 || kid == K_DMA_8) {
+    if (kid == K_DMA_4 || kid == K_DMA_8 || kid == K_DMA_8W) {
         // 16-bit 4M, both operands chunked along k, whole tiles and k-tiles
         if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
         if (g.K % 32) return false;
@@ -1367,6 +1424,7 @@ static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, co
                      const ScaleRefs &sc, hipStream_t st) {
     if (kid == K_DMA_4) return launch_dma_cfg<BF, 256, 128, 2, 2, 3>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_8) return launch_dma_cfg<BF, 256, 128, 4, 2, 3>(A, B, C, g, S, sc, st);
+    if (kid == K_DMA_8W) return launch_dma_cfg<BF, 256, 128, 2, 4, 3>(A, B, C, g, S, sc, st);
     if (al == Algo::M4) {
         switch (kid) {
             case K_MFMA_S: launch_h_cfg<BF, false, 64, 16, 32, 2, 1>(A, B, C, g, S, sc, st); break;
