@@ -152,6 +152,44 @@ def timed_kernels(T, plan, bits, begin, end, dtype_key):
     return fam
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def gemm_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "common.h", "device_util.h"):
+        with open(os.path.join(ROOT, "paper_2407_00769_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if there is none for
+    this kernel and workload or the GEMM sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload, {}).get(kernel)
+    if not e or e.get("sources_sha256") != gemm_source_digest():
+        return None
+    return e["bytes_per_launch"]
+
+
+def calibrate_copy(torch, gib=1, reps=4):
+    """A plain device copy of a known size (for scaling the HBM byte counters)."""
+    n = gib << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": reps}), flush=True)
+
+
 def roofline_entry(fam, dtype_key):
     name, d = max(fam.items(), key=lambda kv: kv[1]["ms"])
     sec = d["ms"] * 1e-3
@@ -212,8 +250,9 @@ def cpu_baseline_einsum(flops_per_slice, seconds_target):
         reps += 1
     dt = time.perf_counter() - t0
     rate = fl * reps / dt
-    return {"value": round(rate / 1e12, 6), "unit": "TFLOP/s", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": f"oracle pairwise contraction (numpy complex128 einsum) of a 2^13 x 2^9 x 2^10 step, "
+    return {"value": round(rate / 1e12, 6), "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle pairwise contraction (numpy complex128 einsum, one thread: numpy's einsum "
+                      f"kernel does not use BLAS) of a 2^13 x 2^9 x 2^10 step, "
                       f"{reps} runs in {dt:.1f} s = {rate / 1e9:.1f} GFLOP/s; estimated "
                       f"{flops_per_slice / rate:.0f} s per slice (no full oracle exists for 53 qubits)",
             "seconds_per_slice": flops_per_slice / rate}
@@ -229,6 +268,8 @@ def main():
     ap.add_argument("--compare", default="c64,f16_3m,bf16_4m")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy 4 times (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): slice blocks on several GPUs "
@@ -237,6 +278,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     import workloads
     from paper_2407_00769_amd import _tnc as T
     from paper_2407_00769_amd import circuit_network as cn
@@ -312,6 +356,7 @@ def main():
     dkey = DKEY[args.prec]
     fam = timed_kernels(T, main_r["plan"], bits, 0, min(w["per_step"], 1 << len(w["sliced"])), dkey)
     roof = roofline_entry(fam, dkey)
+    roof["traffic"] = measured_traffic(roof["kernel"], f"{w['name']}_{args.prec}")
 
     cpu = None
     if not args.no_cpu:

@@ -439,10 +439,25 @@ template <bool BF> __device__ __forceinline__ uint32_t sum_bits(uint32_t w) {
     }
 }
 
-// XCD-aware order: consecutive tiles of one row block land on one XCD (8 per chip).
+// XCD-aware order: blocks are dispatched to the 8 XCDs round-robin, so block
+// w is given tile (w % 8) * (total / 8) + w / 8 and each XCD works through a
+// contiguous range of the tile order.
 __device__ __forceinline__ int64_t xcd_tile(int64_t w, int64_t total) {
     if (total % 8) return w;
     return (w % 8) * (total / 8) + w / 8;
+}
+
+// Tile order in groups of GM row blocks: tile t covers row block
+// g*GM + t % gm and column block (t / gm) % tiles_n of group g, so the ~32
+// tiles an XCD runs at once form a GM x 8 patch whose operand strips are
+// shared through its L2 (a 1 x 32 row would fetch 32 B strips).
+template <int GM>
+__device__ __forceinline__ void tile_coords(int64_t t, int64_t tiles_m, int64_t tiles_n, int64_t &mt, int64_t &nt) {
+    const int64_t per_group = (int64_t)GM * tiles_n;
+    const int64_t g = t / per_group, r = t - g * per_group;
+    const int64_t gm = tiles_m - g * GM < GM ? tiles_m - g * GM : GM;
+    mt = g * GM + r % gm;
+    nt = r / gm;
 }
 
 template <bool BF, bool M3, int BM, int BN, int BK, int WM, int WN>
@@ -484,7 +499,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const int64_t tiles_n = (g.N + BN - 1) / BN;
     const int64_t tiles_m = (g.M + BM - 1) / BM;
     const int64_t t = xcd_tile(blockIdx.x, tiles_m * tiles_n);
-    const int64_t m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
+    int64_t mt, nt;
+    tile_coords<4>(t, tiles_m, tiles_n, mt, nt);
+    const int64_t m0 = mt * BM, n0 = nt * BN;
     float scale = 1.f;
     if (P == 1) {
         int shift = step_shift(sc, s);
@@ -812,7 +829,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const int64_t b = blockIdx.y / P, part = blockIdx.y - b * P;
     const int64_t tiles_n = g.N / BN, tiles_m = g.M / BM;
     const int64_t t = xcd_tile(blockIdx.x, tiles_m * tiles_n);
-    const int64_t m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
+    int64_t mt, nt;
+    tile_coords<4>(t, tiles_m, tiles_n, mt, nt);
+    const int64_t m0 = mt * BM, n0 = nt * BN;
     float scale = 1.f;
     if (P == 1) {
         int shift = step_shift(sc, s);
@@ -1032,7 +1051,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const int64_t tiles_n = (g.N + BN - 1) / BN;
     const int64_t tiles_m = (g.M + BM - 1) / BM;
     const int64_t t = xcd_tile(blockIdx.x, tiles_m * tiles_n);
-    const int64_t m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
+    int64_t mt, nt;
+    tile_coords<4>(t, tiles_m, tiles_n, mt, nt);
+    const int64_t m0 = mt * BM, n0 = nt * BN;
     const float2 *Ap = A + s * g.sA + b * g.bA;
     const float2 *Bp = B + s * g.sB + b * g.bB;
     float2 *Cp = C + s * g.sC + b * g.bC;

@@ -351,6 +351,17 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             return lg == 2 ? 1 : 0;
         };
         int oa = orient(A), ob = orient(B);
+        // On a compute-bound 16-bit 4M step the k-chunked kernels (operands
+        // streamed into LDS as whole k rows) are several times faster than
+        // the ones that transpose in registers: permute an operand that is
+        // stored [k][free] when the permute costs under a tenth of the GEMM
+        // (at 5 TB/s for the permute and 1 PFLOP/s for the GEMM).
+        if (an.dt != Dtype::C64 && an.al == Algo::M4) {
+            const double fl = 8.0 * std::ldexp(1.0, sa[0] + sa[1] + sb[1] + sa[2]);
+            auto cheap = [&](const TensorRec &T) { return 2.0 * es * std::ldexp(1.0, T.rank()) / 5e12 < 0.1 * fl / 1e15; };
+            if (oa == 0 && cheap(A)) oa = -1;
+            if (ob == 0 && cheap(B)) ob = -1;
+        }
         const double szA = std::ldexp(1.0, A.rank()), szB = std::ldexp(1.0, B.rank());
         // batch and k orders must agree between A and B; take them from a kept
         // operand, preferring the larger
