@@ -1,0 +1,88 @@
+"""The 53-qubit workload at reduced depth, checked in full against the oracle.
+
+The benchmark's 53-qubit, 20-cycle network has no full oracle (2^53 states,
+~2.4e14 flops per slice).  Its twin keeps the layout, gate set, seed and the
+correlated-subspace request (12 open qubits under a 41-bit prefix, all 4096
+values) but has 8 cycles; the path search slices it into a few slices.  The
+oracle contracts every slice in FP64 (numpy einsum) along the plan's pairwise
+order -- the order is data, it changes only FP64 rounding -- and sums them,
+which is the value of the whole network.  The GPU sums the same slices in one
+block; each form must match to its tolerance, and slice 0 alone must match
+the oracle's slice 0 (complex64).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import workloads  # noqa: E402
+from oracle import einsum, metrics  # noqa: E402
+
+OPEN = list(range(41, 53))
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_00769_amd import _tnc
+    return _tnc
+
+
+@pytest.fixture(scope="module")
+def twin(T):
+    from paper_2407_00769_amd import circuit_network as cn
+    c = workloads.config_circuit(3, cycles=8)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    ssa, sl, _ = T.tnc_search(net, len(r), OPEN, 22, restarts=32, seed=1)
+    assert 1 <= len(sl) <= 3, len(sl)
+    bits = workloads.subspace_bitstrings(53, OPEN, 5)
+    # oracle: every slice in FP64 along the same order, summed
+    ts = einsum.network_tensors(c, st)
+    closed = {st.output_labels[q]: int((int(bits[0]) >> q) & 1) for q in range(53) if q not in OPEN}
+    out_labels = [st.output_labels[q] for q in OPEN]
+    slices = []
+    for sigma in range(1 << len(sl)):
+        fixed = dict(closed)
+        fixed.update({int(lab): (sigma >> j) & 1 for j, lab in enumerate(sl)})
+        slices.append(einsum.contract_path(ts, out_labels, ssa, fixed))
+    idx = tuple(((bits >> np.uint64(q)) & np.uint64(1)).astype(np.int64) for q in OPEN)
+    ref_all = sum(slices)[idx]
+    ref_0 = slices[0][idx]
+    yield dict(net=net, ssa=ssa, sl=sl, bits=bits, ref_all=ref_all, ref_0=ref_0)
+    T.tnc_network_destroy(net)
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    ws = torch.empty(24 << 30, dtype=torch.uint8, device="cuda:0")
+    c = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    yield c
+    T.tnc_destroy(c)
+    torch.cuda.synchronize()
+    del ws
+
+
+def test_oracle_twin_is_porter_thomas_like(twin):
+    # a random 53-qubit circuit: mean |amp|^2 over the subspace is ~2^-53
+    p = np.abs(twin["ref_all"]) ** 2 * 2.0 ** 53
+    assert 0.5 < p.mean() < 2.0, p.mean()
+
+
+@pytest.mark.parametrize("prec,fmin,rlmax", [("c64", 1 - 1e-8, 1e-4), ("f16_4m", 0.999, 0.05),
+                                             ("f16_3m", 0.999, 0.05), ("bf16_4m", 0.99, 0.2)])
+def test_twin_all_slices_match_oracle(T, ctx, twin, prec, fmin, rlmax):
+    n = 1 << len(twin["sl"])
+    plan = T.tnc_plan_create(ctx, twin["net"], twin["ssa"], twin["sl"], OPEN, prec)
+    out, rep = T.tnc_execute(plan, twin["bits"], 0, n)
+    assert rep["slices"] == n
+    f = metrics.fidelity(twin["ref_all"], out)
+    rl = metrics.rel_l2(out, twin["ref_all"])
+    assert f >= fmin and rl <= rlmax, (prec, f, rl)
+    if prec == "c64":
+        o0, _ = T.tnc_execute(plan, twin["bits"], 0, 1)
+        assert metrics.rel_l2(o0, twin["ref_0"]) <= 1e-4
+    T.tnc_plan_destroy(plan)
