@@ -275,8 +275,12 @@ __global__ void __launch_bounds__(256) gemm_thin_kernel(const W *__restrict__ A,
         if constexpr (M3) Bsum[j][kk] = round_to_storage<W>(v.x + v.y);
     }
     __syncthreads();
-    // vector stores: C chunked along the unit's span
-    const bool vstore = MODE == 0 ? (g.c_nc && NN % V == 0) : (!g.c_nc);
+    // vector stores: along n (V consecutive columns of one row: MODE 0, and
+    // MODE 1 row by row) or along m (the V rows of a MODE 1 unit)
+    constexpr int LV = V == 4 ? 2 : 1;
+    const bool n_vec = NN % V == 0 && g.cn.ls == 0 && g.cn.l >= LV && g.N >= V;
+    const bool m_vec = MODE == 1 && g.cm.ls == 0 && g.cm.l >= LV;
+    const bool vstore = MODE == 0 ? (g.c_nc && n_vec) : (!g.c_nc ? m_vec : n_vec);
     const int64_t units = g.M / R;
     float mx = 0.f;
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < units; u += (int64_t)gridDim.x * blockDim.x) {
@@ -347,7 +351,7 @@ __global__ void __launch_bounds__(256) gemm_thin_kernel(const W *__restrict__ A,
                     }
                     *(Pack16<W> *)(Cp + c_index(g, m, n0 + j0)) = o;
                 }
-            } else {
+            } else if (!g.c_nc) {
 #pragma unroll
                 for (int j = 0; j < NN; j++) {
                     Pack16<W> o;
@@ -359,6 +363,20 @@ __global__ void __launch_bounds__(256) gemm_thin_kernel(const W *__restrict__ A,
                     }
                     *(Pack16<W> *)(Cp + c_index(g, m, n0 + j)) = o;
                 }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; r++)
+#pragma unroll
+                    for (int j0 = 0; j0 < NN; j0 += V) {
+                        Pack16<W> o;
+#pragma unroll
+                        for (int q = 0; q < V; q++) {
+                            float re, im;
+                            value(r, (j0 + q) % NN, re, im);
+                            o.w[q] = make_entry<W, SCALE>(re, im, scale, mx);
+                        }
+                        *(Pack16<W> *)(Cp + c_index(g, m + r, n0 + j0)) = o;
+                    }
             }
         } else {
 #pragma unroll
@@ -380,16 +398,9 @@ static int thin_mode(Dtype dt, const GemmShape &g) {
     const int64_t v = (int64_t)1 << lv;
     if (g.K > 64 || g.N > 16 || g.nb * (g.N / std::min<int64_t>(g.N, 16)) > 65535) return -1;
     auto ok = [&](const Seg &sg, int64_t ext) { return sg.ls == 0 && seg_low_run(sg, ext) >= lv && ext % v == 0; };
-    bool c_ok;
-    if (g.a_kc && ok(g.ak, g.K)) {
-        // vector stores need C chunked along n with whole chunks
-        c_ok = !g.c_nc || std::min<int64_t>(g.N, 16) % v != 0 || ok(g.cn, g.N);
-        return c_ok ? 0 : -1;
-    }
-    if (!g.a_kc && ok(g.am, g.M)) {
-        c_ok = g.c_nc || ok(g.cm, g.M);
-        return c_ok ? 1 : -1;
-    }
+    // the result is written with 16-byte stores where its layout allows, else entry by entry
+    if (g.a_kc && ok(g.ak, g.K)) return 0;
+    if (!g.a_kc && ok(g.am, g.M)) return 1;
     return -1;
 }
 
