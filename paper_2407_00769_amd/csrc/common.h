@@ -132,7 +132,8 @@ enum KernelId : int {
     K_DMA_4 = 8,      // 16-bit 4M, operands streamed into LDS by DMA; 4 waves
     K_DMA_8 = 9,      // the same with 8 waves (4 x 2)
     K_DMA_8W = 10,    // 8 waves as 2 x 4 (wider wave tiles along n)
-    K_COUNT = 11
+    K_DMA_2 = 11,     // 128 x 128 tile, two stages: two blocks per CU (short k)
+    K_COUNT = 12
 };
 const char *kernel_name(int k);
 // Segments of the plain layouts ([m][k] or [k][m] etc., as the chunk flags
