@@ -133,7 +133,9 @@ enum KernelId : int {
     K_DMA_8 = 9,      // the same with 8 waves (4 x 2)
     K_DMA_8W = 10,    // 8 waves as 2 x 4 (wider wave tiles along n)
     K_DMA_2 = 11,     // 128 x 128 tile, two stages: two blocks per CU (short k)
-    K_COUNT = 12
+    K_DMA_N64 = 12,   // 256 x 64 tile, two stages, two blocks per CU (narrow n, HBM-bound)
+    K_DMA_N32 = 13,   // 256 x 32 tile, the same
+    K_COUNT = 14
 };
 const char *kernel_name(int k);
 // Segments of the plain layouts ([m][k] or [k][m] etc., as the chunk flags

@@ -810,9 +810,9 @@ struct DTile {
     static constexpr int A_PER = BM / 8 / (NT / 64);             // 1 KB DMA blocks per wave and stage
     static constexpr int B_PER = BN / 8 / (NT / 64);
     static constexpr int LPT = A_PER + B_PER;                    // DMA loads per thread and stage
-    // a 128 x 128 tile with two stages takes 64 KB of LDS: its registers are
-    // sized for two blocks per CU (see the launch bounds of the kernel)
-    static_assert(BM * BN > 128 * 128 || LDS_BYTES <= 80 * 1024, "two blocks per CU");
+    // two-stage variants fit two blocks per CU in LDS; their registers are
+    // sized for that (see the launch bounds of the kernel)
+    static_assert(STAGES != 2 || LDS_BYTES <= 80 * 1024, "two blocks per CU");
     static_assert(FM >= 1 && FC >= 1, "wave tile too small");
     static_assert(A_PER >= 1 && B_PER >= 1 && A_PER * (NT / 64) * 8 == BM && B_PER * (NT / 64) * 8 == BN, "DMA split");
     static_assert(STAGES >= 2 && LPT * (STAGES - 2) < 64, "stages");
@@ -830,7 +830,7 @@ template <int VM_AHEAD, int LPT> __device__ __forceinline__ void ring_wait_for(i
 }
 
 template <bool BF, int BM, int BN, int WM, int WN, int STAGES>
-__global__ void __launch_bounds__(64 * WM * WN, (BM * BN <= 128 * 128 ? 2 : 1))
+__global__ void __launch_bounds__(64 * WM * WN, (STAGES == 2 ? 2 : 1))
     gemm_dma_h_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t *__restrict__ C,
                       GemmShape g, ScaleRefs sc) {
     using Tl = DTile<BM, BN, WM, WN, STAGES>;
@@ -1279,6 +1279,8 @@ const char *kernel_name(int k) {
         case K_DMA_8: return "dma_8";
         case K_DMA_8W: return "dma_8w";
         case K_DMA_2: return "dma_2";
+        case K_DMA_N64: return "dma_n64";
+        case K_DMA_N32: return "dma_n32";
         default: return "?";
     }
 }
@@ -1309,6 +1311,8 @@ static TileCfg tile_of(int kid, Dtype dt, Algo al) {
             case K_DMA_8: return {256, 128};
             case K_DMA_8W: return {256, 128};
             case K_DMA_2: return {128, 128};
+            case K_DMA_N64: return {256, 64};
+            case K_DMA_N32: return {256, 32};
         }
     } else {
         switch (kid) {
@@ -1333,7 +1337,7 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
     if (g.nb > 65535) return false;
     if (kid < 0 || kid >= K_COUNT) return false;
     if (dt == Dtype::C64 && al == Algo::M3) return false;
-    if (kid == K_DMA_4 || kid == K_DMA_8 || kid == K_DMA_8W || kid == K_DMA_2) {
+    if (kid >= K_DMA_4 && kid <= K_DMA_N32) {
         // 16-bit 4M, both operands chunked along k, whole tiles and k-tiles
         if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
         if (g.K % 32) return false;
@@ -1463,6 +1467,8 @@ static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, co
     if (kid == K_DMA_8) return launch_dma_cfg<BF, 256, 128, 4, 2, 3>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_8W) return launch_dma_cfg<BF, 256, 128, 2, 4, 3>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_2) return launch_dma_cfg<BF, 128, 128, 2, 2, 2>(A, B, C, g, S, sc, st);
+    if (kid == K_DMA_N64) return launch_dma_cfg<BF, 256, 64, 4, 2, 2>(A, B, C, g, S, sc, st);
+    if (kid == K_DMA_N32) return launch_dma_cfg<BF, 256, 32, 4, 1, 2>(A, B, C, g, S, sc, st);
     if (al == Algo::M4) {
         switch (kid) {
             case K_MFMA_S: launch_h_cfg<BF, false, 64, 16, 32, 2, 1>(A, B, C, g, S, sc, st); break;
