@@ -272,6 +272,46 @@ int tnc_mlp_set_params(tnc_ctx *ctx, const float *params);
  * on this thread. */
 int tnc_costmodel_use(tnc_ctx *ctx);
 
+/* ------------------------------------------------------------------ low-precision exchange codec */
+
+/* Quantization of the data a sub-network exchanges (paper Sec. 3.2, Eq.
+ * quantcal with the parameters of Table quanttable).  A group of real values
+ * y = sign(x)|x|^exp is mapped to q = y * scale + zero with
+ *     scale = (q_max - q_min) / (max y - min y),
+ *     zero  = (q_min max y - q_max min y) / (max y - min y),
+ * rounded half-to-even and clamped for the integer kinds; decoding inverts
+ * the map.  A complex tensor is coded as the real array of its interleaved
+ * (re, im) float32 values (n = 2 x entries).  Kinds:
+ *   TNC_Q_HALF  q in +-65504, exp 1, one group (the whole tensor), 2 bytes per value (FP16)
+ *   TNC_Q_INT8  q in -128..127, exp 0.2, one group, 1 byte per value
+ *   TNC_Q_INT4  q in 0..15, exp 1, groups of `group` values (a power of two,
+ *               16..1024; 0 = 128), half a byte per value, value 2j in the low
+ *               nibble of byte j; the last group may be short, and an unused
+ *               high nibble is 0
+ * The integer decision is taken in float32 with each operation rounded (no
+ * fused multiply-add).  A group whose values are all equal gets scale 1 and
+ * zero = q_min - value.  Values must be finite.
+ * The compression rate of Eq. compress is (4 n_groups + 4 n_groups +
+ * code_bytes) / (4 n). */
+#define TNC_Q_HALF 0
+#define TNC_Q_INT8 1
+#define TNC_Q_INT4 2
+
+/* Sizes for n values: bytes of codes and number of groups (host outputs,
+ * either may be NULL).  TNC_EINVAL for an unknown kind or group size (half
+ * and int8 take group 0). */
+int tnc_quant_sizes(int32_t kind, int64_t n, int32_t group, int64_t *code_bytes, int64_t *n_groups);
+/* Quantize n float32 values x (device, 16-byte aligned) into codes (device,
+ * 16-byte aligned, tnc_quant_sizes bytes), scales and zeros (device float32,
+ * one per group).  Runs on the context's stream and waits for it; ms_out
+ * (host, may be NULL) receives the device time of the kernels. */
+int tnc_quantize(tnc_ctx *ctx, int32_t kind, int64_t n, const float *x, int32_t group, void *codes,
+                 float *scales, float *zeros, double *ms_out);
+/* Decode n values from codes, scales and zeros (device) into x (device,
+ * 16-byte aligned, float32).  Same stream and timing behaviour. */
+int tnc_dequantize(tnc_ctx *ctx, int32_t kind, int64_t n, const void *codes, const float *scales,
+                   const float *zeros, int32_t group, float *x, double *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,10 +31,11 @@ Readings where the paper is silent (stated here and in the design notes):
 
 Two arithmetics are provided.  ``precision="fp64"`` is the definition,
 evaluated in double precision.  ``precision="fp32"`` takes the integer
-decision the way a float32 implementation does -- the power in double
-rounded to float32, scale and zero formed in float32, then q = y * scale
-rounded, plus zero rounded (no fused multiply-add) -- so that codes produced
-by another float32 implementation of the same steps can be compared exactly.
+decision the way a float32 implementation does -- the power with float32
+powf, scale and zero formed in float32, then q = y * scale rounded, plus
+zero rounded (no fused multiply-add) -- so that codes produced by another
+float32 implementation of the same steps agree, except where two powf
+implementations differ in the last place next to a rounding tie.
 """
 from __future__ import annotations
 
@@ -64,6 +65,14 @@ def _power(x: np.ndarray, e: float) -> np.ndarray:
     return x if e == 1.0 else np.sign(x) * np.abs(x) ** e
 
 
+def _power32(x: np.ndarray, e: float) -> np.ndarray:
+    """sign(x)|x|^e in float32 (C powf on |x| with the float32 exponent)."""
+    x = np.asarray(x, np.float32)
+    if e == 1.0:
+        return x
+    return (np.sign(x) * np.power(np.abs(x), np.float32(e))).astype(np.float32)
+
+
 def group_bounds(n: int, kind: str, group: int | None = None):
     g = KINDS[kind]["group"] if group is None else group
     if g <= 0 or g >= n:
@@ -76,9 +85,7 @@ def quantize(x, kind: str, group: int | None = None, precision: str = "fp64"):
     (int8/int4) or FP16 values (half, as float16)."""
     p = KINDS[kind]
     x = np.asarray(x, np.float32 if precision == "fp32" else np.float64).ravel()
-    y = _power(x, p["exp"])
-    if precision == "fp32":
-        y = y.astype(np.float32)
+    y = _power32(x, p["exp"]) if precision == "fp32" else _power(x, p["exp"])
     ft = np.float32 if precision == "fp32" else np.float64
     qmin, qmax = ft(p["qmin"]), ft(p["qmax"])
     bounds = group_bounds(x.size, kind, group)
@@ -107,7 +114,7 @@ def unrounded(x, kind: str, group: int | None = None) -> np.ndarray:
     """The float32 value each code is rounded from (for telling near-ties)."""
     p = KINDS[kind]
     x = np.asarray(x, np.float32).ravel()
-    y = _power(x, p["exp"]).astype(np.float32)
+    y = _power32(x, p["exp"])
     _c, sc, ze = quantize(x, kind, group, "fp32")
     out = np.empty(x.size, np.float64)
     for gi, (a, b) in enumerate(group_bounds(x.size, kind, group)):

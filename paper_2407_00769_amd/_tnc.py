@@ -76,6 +76,11 @@ _SIGS = {
                                         c_int32_p, ctypes.c_int, ctypes.POINTER(tnc_plan_stats)]),
     "tnc_execute": (ctypes.c_int, [vp, ctypes.c_int64, c_u64_p, ctypes.c_int64, ctypes.c_int64, vp,
                                    ctypes.POINTER(tnc_report)]),
+    "tnc_quant_sizes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "tnc_quantize": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_int32, vp, vp, vp, c_double_p]),
+    "tnc_dequantize": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp,
+                                      c_double_p]),
     "tnc_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int32]),
     "tnc_plan_step_times": (ctypes.c_int, [vp, ctypes.c_int32, c_double_p, c_double_p, c_int32_p]),
     "tnc_plan_steps": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, c_int32_p, c_int32_p, c_int32_p, c_double_p,
@@ -354,3 +359,41 @@ def tnc_mlp_set_params(ctx, params):
 
 def tnc_costmodel_use(ctx):
     _check(lib.tnc_costmodel_use(ctx))
+
+
+QKINDS = {"half": 0, "int8": 1, "int4": 2}
+
+
+def tnc_quant_sizes(kind, n, group=0):
+    cb, ng = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib.tnc_quant_sizes(QKINDS.get(kind, kind), int(n), int(group), ctypes.byref(cb), ctypes.byref(ng)))
+    return cb.value, ng.value
+
+
+def tnc_quantize(ctx, kind, x, group=0):
+    """x: contiguous float32 device tensor.  Returns (codes uint8 tensor,
+    scales, zeros (float32 tensors), device ms)."""
+    import torch
+    k = QKINDS.get(kind, kind)
+    n = x.numel()
+    cb, ng = tnc_quant_sizes(k, n, group)
+    codes = torch.empty(max(cb, 16), dtype=torch.uint8, device=x.device)
+    scales = torch.empty(max(ng, 1), dtype=torch.float32, device=x.device)
+    zeros = torch.empty(max(ng, 1), dtype=torch.float32, device=x.device)
+    torch.cuda.synchronize(x.device)
+    ms = ctypes.c_double(0)
+    _check(lib.tnc_quantize(ctx, k, n, _dptr(x), int(group), _dptr(codes), _dptr(scales), _dptr(zeros),
+                            ctypes.byref(ms)))
+    return codes[:cb], scales[:ng], zeros[:ng], ms.value
+
+
+def tnc_dequantize(ctx, kind, n, codes, scales, zeros, group=0):
+    """Returns (float32 device tensor of n values, device ms)."""
+    import torch
+    k = QKINDS.get(kind, kind)
+    x = torch.empty(max(n, 4), dtype=torch.float32, device=codes.device)
+    torch.cuda.synchronize(codes.device)
+    ms = ctypes.c_double(0)
+    _check(lib.tnc_dequantize(ctx, k, int(n), _dptr(codes), _dptr(scales), _dptr(zeros), int(group), _dptr(x),
+                              ctypes.byref(ms)))
+    return x[:n], ms.value

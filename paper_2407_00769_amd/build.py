@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtnc.so")
-SOURCES = ["kernels.hip", "gemm.hip", "mlp.hip", "planner.cpp", "engine.cpp", "contract.cpp", "search.cpp"]
+SOURCES = ["kernels.hip", "gemm.hip", "mlp.hip", "codec.hip", "planner.cpp", "engine.cpp", "contract.cpp",
+           "search.cpp", "codec.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -21,11 +22,16 @@ FLAGS = [
 ]
 
 
+# the codec takes its integer decisions with every float32 operation rounded
+# on its own: no contraction into fused multiply-adds there
+EXTRA = {"codec.hip": ["-ffp-contract=off"]}
+
+
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + lang + ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
