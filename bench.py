@@ -190,6 +190,59 @@ def calibrate_copy(torch, gib=1, reps=4):
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": reps}), flush=True)
 
 
+def codec_bench(torch, T, n_entries=1 << 27, reps=5, cpu_seconds=10.0):
+    """Throughput of the exchange codec (quantize, dequantize) on a complex64
+    tensor of n_entries (2 n_entries float32 values), against HBM bandwidth;
+    the oracle's numpy codec timed on a bounded sample beside it."""
+    from oracle import codec as ocodec
+    n = 2 * n_entries
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
+    ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    g = torch.Generator(device="cuda:0").manual_seed(11)
+    x = torch.randn(n, dtype=torch.float32, device="cuda:0", generator=g)
+    out = {}
+    for kind in ("half", "int8", "int4"):
+        cb, ng = T.tnc_quant_sizes(kind, n)
+        qms, dms = [], []
+        for _ in range(reps):
+            codes, sc, ze, ms = T.tnc_quantize(ctx, kind, x)
+            qms.append(ms)
+            _xr, ms2 = T.tnc_dequantize(ctx, kind, n, codes, sc, ze)
+            dms.append(ms2)
+        q, d = min(qms), min(dms)
+        # algorithmic bytes: whole-tensor kinds read the values twice (extremes, then codes)
+        q_bytes = (8 if kind != "int4" else 4) * n + cb + 8 * ng
+        d_bytes = cb + 8 * ng + 4 * n
+        out[kind] = {"quantize_ms": round(q, 3), "quantize_gbs": round(q_bytes / q / 1e6, 1),
+                     "dequantize_ms": round(d, 3), "dequantize_gbs": round(d_bytes / d / 1e6, 1),
+                     "compression_rate": round(ocodec.compression_rate(n, kind), 5)}
+    T.tnc_destroy(ctx)
+    # the oracle on a sample of about cpu_seconds
+    xs = np.random.default_rng(0).normal(size=1 << 22).astype(np.float32)
+    t0 = time.perf_counter()
+    reps_cpu = 0
+    while time.perf_counter() - t0 < cpu_seconds:
+        for kind in ("half", "int8", "int4"):
+            c, s_, z_ = ocodec.quantize(xs, kind, precision="fp32")
+            ocodec.dequantize(c, s_, z_, kind)
+        reps_cpu += 1
+    dt = time.perf_counter() - t0
+    cpu_rate = 3 * reps_cpu * xs.size * 4 / dt / 1e9
+    best = max(out.values(), key=lambda v: v["quantize_gbs"])
+    return {"metric": "exchange codec throughput (quantize + dequantize of a complex64 tensor)",
+            "value": round(min(v["quantize_gbs"] for v in out.values()), 1), "unit": "GB/s",
+            "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"2^{n_entries.bit_length() - 1}-entry complex64 tensor (2^{n.bit_length() - 1} "
+                                   f"float32 values), N(0,1) values"},
+            "kinds": out,
+            "roofline": {"bound": "hbm", "peak": HBM_GBS, "unit": "GB/s",
+                         "frac_best": round(best["quantize_gbs"] / HBM_GBS, 4)},
+            "cpu_baseline": {"value": round(cpu_rate, 4), "unit": "GB/s of float32 input (quantize + dequantize)",
+                             "cores": 1, "kind": "oracle",
+                             "sample": f"oracle codec (numpy, float32 decisions) on 2^22 values, all three kinds, "
+                                       f"{reps_cpu} rounds in {dt:.1f} s"}}
+
+
 def roofline_entry(fam, dtype_key):
     name, d = max(fam.items(), key=lambda kv: kv[1]["ms"])
     sec = d["ms"] * 1e-3
@@ -270,6 +323,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy 4 times (reference for the HBM byte counters)")
+    ap.add_argument("--codec", action="store_true",
+                    help="only measure the low-precision exchange codec (its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): slice blocks on several GPUs "
@@ -283,6 +338,9 @@ def main():
         return
     import workloads
     from paper_2407_00769_amd import _tnc as T
+    if args.codec:
+        print(json.dumps(codec_bench(torch, T)), flush=True)
+        return
     from paper_2407_00769_amd import circuit_network as cn
 
     assert torch.cuda.is_available(), "no GPU"

@@ -311,6 +311,12 @@ int tnc_quantize(tnc_ctx *ctx, int32_t kind, int64_t n, const float *x, int32_t 
  * 16-byte aligned, float32).  Same stream and timing behaviour. */
 int tnc_dequantize(tnc_ctx *ctx, int32_t kind, int64_t n, const void *codes, const float *scales,
                    const float *zeros, int32_t group, float *x, double *ms_out);
+/* Pass the result of path step `step` of a complex64 plan through the codec
+ * (quantize, then dequantize in place, each slice on its own) on every later
+ * tnc_execute, as if that tensor were exchanged between devices (paper Sec.
+ * 3.2; the single-step quantization study of Sec. 4.3.1).  step = -1 switches it off.
+ * The plan allocates the code buffers.  TNC_EUNSUPPORTED for 16-bit plans. */
+int tnc_plan_set_codec(tnc_plan *plan, int32_t step, int32_t kind, int32_t group);
 
 #ifdef __cplusplus
 }

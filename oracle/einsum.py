@@ -153,12 +153,16 @@ def brute_force(tensors, output_labels, fixed=None):
     return res
 
 
-def contract_path(tensors, output_labels, ssa, fixed=None):
+def contract_path(tensors, output_labels, ssa, fixed=None, after_step=None):
     """Contract along a given pairwise order (SSA pairs: ids >= len(tensors)
     name earlier results).  The network's value does not depend on the order
     in exact arithmetic, so the order only changes FP64 rounding; it is data
     here, not arithmetic.  A label is summed when no other live tensor and no
-    output holds it."""
+    output holds it.
+
+    ``after_step(s, labels, data) -> data`` may replace the result of pair s
+    (the single-step quantization study of Sec. 4.3.1 passes one step's
+    result through the exchange codec of Sec. 3.2)."""
     ts = fix_labels(tensors, fixed or {})
     out = tuple(l for l in output_labels if not (fixed and l in fixed))
     outset = set(out)
@@ -177,6 +181,8 @@ def contract_path(tensors, output_labels, ssa, fixed=None):
             if l in outset or others > 0:
                 keep.add(l)
         lc, dc = _pair(live[i], live[j], keep)
+        if after_step is not None:
+            dc = after_step(s, lc, dc)
         for l in set(la) | set(lb):
             count[l] -= (l in la) + (l in lb)
         for l in lc:

@@ -81,6 +81,7 @@ _SIGS = {
     "tnc_quantize": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_int32, vp, vp, vp, c_double_p]),
     "tnc_dequantize": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp,
                                       c_double_p]),
+    "tnc_plan_set_codec": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "tnc_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int32]),
     "tnc_plan_step_times": (ctypes.c_int, [vp, ctypes.c_int32, c_double_p, c_double_p, c_int32_p]),
     "tnc_plan_steps": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, c_int32_p, c_int32_p, c_int32_p, c_double_p,
@@ -397,3 +398,7 @@ def tnc_dequantize(ctx, kind, n, codes, scales, zeros, group=0):
     _check(lib.tnc_dequantize(ctx, k, int(n), _dptr(codes), _dptr(scales), _dptr(zeros), int(group), _dptr(x),
                               ctypes.byref(ms)))
     return x[:n], ms.value
+
+
+def tnc_plan_set_codec(plan, step, kind="int4", group=0):
+    _check(lib.tnc_plan_set_codec(plan, int(step), QKINDS.get(kind, kind), int(group)))

@@ -6,13 +6,6 @@
 
 using namespace tnc;
 
-namespace tnc {
-void launch_quantize(int kind, int64_t n, int group, const float *x, void *codes, float *scales, float *zeros,
-                     float2 *part, hipStream_t st);
-void launch_dequantize(int kind, int64_t n, int group, const void *codes, const float *scales, const float *zeros,
-                       float *x, hipStream_t st);
-}  // namespace tnc
-
 namespace {
 
 int resolve_group(int32_t kind, int32_t group) {

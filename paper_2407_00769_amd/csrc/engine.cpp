@@ -153,8 +153,9 @@ extern "C" int tnc_network_destroy(tnc_network *net) {
 static void free_plan_device(tnc_plan *p) {
     for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
     p->graphs.clear();
-    void *ptrs[] = {p->d_leafdata, p->d_desc, p->d_maxw, p->d_expw, p->d_shift, p->d_growth,
-                    p->d_flags,    p->d_params, p->d_bits, p->d_acc, p->d_qob, p->d_part};
+    void *ptrs[] = {p->d_leafdata, p->d_desc, p->d_maxw,  p->d_expw,  p->d_shift, p->d_growth, p->d_flags,
+                    p->d_params,   p->d_bits, p->d_acc,   p->d_qob,   p->d_part,  p->d_codes,  p->d_qscale,
+                    p->d_qzero};
     for (void *q : ptrs)
         if (q) hipFree(q);
 }
@@ -555,6 +556,16 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
     }
     if (tm) HIP_CHECK(hipEventRecord(tm->e[1], st));
     launch_gemm(rec.kernel, dt, an.al, pa, pb, ws + Z.off, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+    if (s == p->codec_step) {
+        // the result of this step passes through the exchange codec, one
+        // slice at a time, as if it were sent to another device
+        for (int q = 0; q < Sl; q++) {
+            float *zr = (float *)(ws + Z.off) + (int64_t)q * 2 * nz;
+            launch_quantize(p->codec_kind, 2 * nz, p->codec_group, zr, p->d_codes, p->d_qscale, p->d_qzero,
+                            (float2 *)p->ctx->small, st);
+            launch_dequantize(p->codec_kind, 2 * nz, p->codec_group, p->d_codes, p->d_qscale, p->d_qzero, zr, st);
+        }
+    }
     if (tm) HIP_CHECK(hipEventRecord(tm->e[2], st));
 }
 
@@ -621,6 +632,41 @@ void enqueue_block(tnc_plan *p, int64_t nsl, int64_t nbits, hipStream_t st, bool
 }
 
 }  // namespace
+
+extern "C" int tnc_plan_set_codec(tnc_plan *plan, int32_t step, int32_t kind, int32_t group) {
+    API_BEGIN
+    REQUIRE(plan, "plan is NULL");
+    REQUIRE(step >= -1 && step < (int)plan->an.steps.size(), "step out of range");
+    if (step >= 0 && plan->an.dt != Dtype::C64)
+        TNC_THROW(TNC_EUNSUPPORTED, "the codec round trip applies to complex64 plans (float32 values)");
+    int64_t cb = 0, ng = 0;
+    if (step >= 0) {
+        // per-slice results sit nz complex values apart; the codec's vector
+        // loads need each slice 16-byte aligned, so nz >= 2
+        const int rz = plan->an.tensors[plan->an.steps[step].z].rank();
+        if (rz < 1) TNC_THROW(TNC_EUNSUPPORTED, "the codec round trip needs a result of rank >= 1");
+        const int64_t n = 2 * ((int64_t)1 << rz);
+        int rc = tnc_quant_sizes(kind, n, group, &cb, &ng);
+        if (rc != TNC_OK) return rc;
+    }
+    HIP_CHECK(hipSetDevice(plan->ctx->device));
+    HIP_CHECK(hipStreamSynchronize(plan->ctx->stream));
+    for (auto &kv : plan->graphs) hipGraphExecDestroy(kv.second);
+    plan->graphs.clear();
+    for (void *q : {(void *)plan->d_codes, (void *)plan->d_qscale, (void *)plan->d_qzero})
+        if (q) HIP_CHECK(hipFree(q));
+    plan->d_codes = nullptr;
+    plan->d_qscale = plan->d_qzero = nullptr;
+    plan->codec_step = step;
+    plan->codec_kind = kind;
+    plan->codec_group = kind == TNC_Q_INT4 && group == 0 ? 128 : group;
+    if (step >= 0) {
+        plan->d_codes = dev_alloc<uint8_t>(cb + 16);
+        plan->d_qscale = dev_alloc<float>(ng);
+        plan->d_qzero = dev_alloc<float>(ng);
+    }
+    API_END
+}
 
 extern "C" int tnc_plan_set_timing(tnc_plan *plan, int32_t on) {
     API_BEGIN

@@ -17,6 +17,13 @@ struct Mlp;   // learned step-cost model (mlp.hip)
 void mlp_free(Mlp *m);
 }
 
+namespace tnc {
+void launch_quantize(int kind, int64_t n, int group, const float *x, void *codes, float *scales, float *zeros,
+                     float2 *part, hipStream_t st);
+void launch_dequantize(int kind, int64_t n, int group, const void *codes, const float *scales, const float *zeros,
+                       float *x, hipStream_t st);
+}  // namespace tnc
+
 struct tnc_ctx {
     int device = 0;
     uint8_t *ws = nullptr;
@@ -62,4 +69,8 @@ struct tnc_plan {
     bool timing = false;
     std::vector<double> step_ms, perm_ms;
     std::vector<int> step_launches;
+    // exchange codec round trip applied to one step's result (complex64 plans)
+    int codec_step = -1, codec_kind = 0, codec_group = 0;
+    void *d_codes = nullptr;
+    float *d_qscale = nullptr, *d_qzero = nullptr;
 };

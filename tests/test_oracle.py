@@ -207,3 +207,36 @@ def test_contract_path_equals_own_order_and_statevector():
         np.testing.assert_allclose(got, ref, atol=1e-12)
     psi = statevector.simulate(c)
     np.testing.assert_allclose(ref.reshape(-1), psi, atol=1e-12)
+
+
+def test_contract_path_step_hook_is_linear():
+    """The network's value is linear in every intermediate result, so scaling
+    step s's result by lam scales the value by lam; the identity hook changes
+    nothing, and the labels handed to the hook are the pair's kept labels."""
+    c = _tiny(2, 3, 5, 17)
+    st = workloads.tn_structure(c)
+    ts = einsum.network_tensors(c, st)
+    ref = einsum.contract(ts, st.output_labels)
+    labels = {i: set(t[0]) for i, t in enumerate(ts)}
+    ssa, nxt = [], len(ts)
+    while len(labels) > 1:
+        i, j = next((i, j) for i in sorted(labels) for j in sorted(labels) if i < j and labels[i] & labels[j])
+        labels[nxt] = labels.pop(i) ^ labels.pop(j)
+        ssa += [i, j]
+        nxt += 1
+    n_steps = len(ssa) // 2
+    seen = []
+
+    def ident(s, lab, d):
+        assert d.shape == (2,) * len(lab)
+        seen.append(s)
+        return d
+
+    np.testing.assert_array_equal(einsum.contract_path(ts, st.output_labels, ssa, after_step=ident),
+                                  einsum.contract_path(ts, st.output_labels, ssa))
+    assert seen == list(range(n_steps))
+    for s in (0, n_steps // 2, n_steps - 1):
+        lam = 0.5 - 1.25j
+        got = einsum.contract_path(ts, st.output_labels, ssa,
+                                   after_step=lambda t, lab, d, s=s: d * lam if t == s else d)
+        np.testing.assert_allclose(got, lam * ref, atol=1e-12)
