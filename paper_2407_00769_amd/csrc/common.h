@@ -156,6 +156,7 @@ void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void 
 void launch_convert_c128(const double *src, int64_t n, Dtype dt, void *dst, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
+void launch_fill_random(Dtype dt, void *p, int64_t n_words, uint32_t seed, hipStream_t st);
 void launch_tensor_max(Dtype dt, const void *x, int64_t n, int S, int64_t slice_stride,
                        uint32_t *max_out, hipStream_t st);
 void launch_accumulate(Dtype dt, const void *R, int rank, int S, int64_t slice_stride,

@@ -46,6 +46,34 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t st) {
     HIP_CHECK(hipGetLastError());
 }
 
+// Operand stand-ins for the autotuner: each 32-bit word gets a hash of its
+// index mapped to two 16-bit values (or one float) uniform in [-1, 1), so the
+// timed kernels toggle their matrix cores as on real data (a loaded GPU's
+// clock depends on it).
+__global__ void fill_random_kernel(uint32_t *p, int64_t n_words, uint32_t seed, int kind) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 0x9E3779B1u ^ (uint32_t)(i >> 32) * 0x85EBCA77u ^ seed;
+        h ^= h >> 16;
+        h *= 0x7FEB352Du;
+        h ^= h >> 15;
+        h *= 0x846CA68Bu;
+        h ^= h >> 16;
+        const float lo = (float)(h & 0xffffu) * (1.f / 32768.f) - 1.f, hi = (float)(h >> 16) * (1.f / 32768.f) - 1.f;
+        if (kind == 0) p[i] = __float_as_uint((float)(h >> 8) * (1.f / 8388608.f) - 1.f);
+        else if (kind == 1) p[i] = f2h_bits(lo) | (f2h_bits(hi) << 16);
+        else p[i] = f2bf_bits(lo) | (f2bf_bits(hi) << 16);
+    }
+}
+
+void launch_fill_random(Dtype dt, void *p, int64_t n_words, uint32_t seed, hipStream_t st) {
+    if (n_words <= 0) return;
+    const int kind = dt == Dtype::C64 ? 0 : (dt == Dtype::BF16 ? 2 : 1);
+    hipLaunchKernelGGL(fill_random_kernel, dim3(grid_for(n_words, 256, 16384)), dim3(256), 0, st, (uint32_t *)p,
+                       n_words, seed, kind);
+    HIP_CHECK(hipGetLastError());
+}
+
 // ===================================================================== permute (bit permutation)
 //
 // dst[s][j] = src[s * src_slice_stride + slice_off[s] + sum_b bit_b(j) * stride[b]]
