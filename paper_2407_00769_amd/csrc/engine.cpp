@@ -346,25 +346,46 @@ double autotune_plan(tnc_plan *p) {
     uint8_t *ws = p->ctx->ws;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     tune_cache_load();
-    // scale bookkeeping for tuning launches lives in the context's small buffer
-    struct Small {
-        uint32_t maxA, maxB, maxC, flag;
-        int growth, shift, pad0, pad1;
-        double expA, expB, expC;
-    } h{0x3f800000u, 0x3f800000u, 0u, 0u, kTargetLog2Host, 0, 0, 0, 0.0, 0.0, 0.0};
-    HIP_CHECK(hipMemcpyAsync(p->ctx->small, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    // Scale bookkeeping for the tuning launches: the producers' maxima and
+    // exponents are one shared entry each (index stride 0), the per-slice
+    // outputs (max |C|, exponent, shift) get S entries, since a launch covers
+    // up to S slices.
+    const int64_t S_t = p->S;
+    const size_t off_maxc = 64, off_shift = off_maxc + 4 * S_t, off_expc = (off_shift + 4 * S_t + 7) & ~(size_t)7;
+    const size_t tune_bytes = off_expc + 8 * S_t;
+    uint8_t *tbuf = nullptr;
+    HIP_CHECK(hipMalloc((void **)&tbuf, tune_bytes));
+    struct FreeOnExit {
+        uint8_t *ptr;
+        hipStream_t st;
+        ~FreeOnExit() {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(ptr);
+        }
+    } free_tbuf{tbuf, st};
+    struct Head {
+        uint32_t maxA, maxB, flag;
+        int growth;
+        double expA, expB;
+    } h{0x3f800000u, 0x3f800000u, 0u, kTargetLog2Host, 0.0, 0.0};
+    HIP_CHECK(hipMemsetAsync(tbuf, 0, tune_bytes, st));
+    HIP_CHECK(hipMemcpyAsync(tbuf, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    Small *d = (Small *)p->ctx->small;
+    Head *d = (Head *)tbuf;
     ScaleRefs sc{};
     sc.maxA = &d->maxA;
+    sc.mA = 0;
     sc.maxB = &d->maxB;
-    sc.maxC = &d->maxC;
+    sc.mB = 0;
+    sc.maxC = (uint32_t *)(tbuf + off_maxc);
     sc.flag = &d->flag;
     sc.growth = &d->growth;
-    sc.shift = &d->shift;
+    sc.shift = (int *)(tbuf + off_shift);
     sc.expA = &d->expA;
+    sc.eA = 0;
     sc.expB = &d->expB;
-    sc.expC = &d->expC;
+    sc.eB = 0;
+    sc.expC = (double *)(tbuf + off_expc);
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
