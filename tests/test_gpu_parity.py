@@ -356,3 +356,27 @@ def test_config2_full_block_matches_oracle(T, ctx, prec):
     T.tnc_network_destroy(net)
     del ws
     torch.cuda.empty_cache()
+
+
+def test_tuning_with_thousands_of_slices_in_flight(T, ctx):
+    """Plan-time tuning launches cover every slice in flight; their per-slice
+    scale bookkeeping must stay inside the library's own buffers.  Device state
+    allocated beside them (the cost model's parameters here) is unchanged, and
+    the plan's amplitudes match the state vector."""
+    from oracle import mlp as omlp
+    canary = omlp.init(11).astype(np.float32)
+    T.tnc_mlp_set_params(ctx, canary)
+    open_q = list(range(16, 20))
+    c, st, net, ssa, sl = _circuit_plan(T, ctx, None, "f16_4m", 8, open_q, cycles=12, seed=21, restarts=2,
+                                        rect=(4, 5))
+    assert len(sl) >= 12, len(sl)
+    plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
+    assert T.tnc_plan_info(plan)["slices_in_flight"] >= 1024
+    np.testing.assert_array_equal(T.tnc_mlp_get_params(ctx), canary)
+    bits = workloads.prefix_bitstrings(20, open_q, 16, 4)
+    out, rep = T.tnc_execute(plan, bits, 0, 1 << len(sl))
+    ref = statevector.amplitudes(c, bits)
+    assert metrics.fidelity(ref, out) >= 0.999
+    np.testing.assert_array_equal(T.tnc_mlp_get_params(ctx), canary)
+    T.tnc_plan_destroy(plan)
+    T.tnc_network_destroy(net)
