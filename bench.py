@@ -194,7 +194,6 @@ def codec_bench(torch, T, n_entries=1 << 27, reps=5, cpu_seconds=10.0):
     """Throughput of the exchange codec (quantize, dequantize) on a complex64
     tensor of n_entries (2 n_entries float32 values), against HBM bandwidth;
     the oracle's numpy codec timed on a bounded sample beside it."""
-    from oracle import codec as ocodec
     n = 2 * n_entries
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
     ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
@@ -215,9 +214,73 @@ def codec_bench(torch, T, n_entries=1 << 27, reps=5, cpu_seconds=10.0):
         d_bytes = cb + 8 * ng + 4 * n
         out[kind] = {"quantize_ms": round(q, 3), "quantize_gbs": round(q_bytes / q / 1e6, 1),
                      "dequantize_ms": round(d, 3), "dequantize_gbs": round(d_bytes / d / 1e6, 1),
-                     "compression_rate": round(ocodec.compression_rate(n, kind), 5)}
+                     "compression_rate": round(compression_rate(T, kind, n), 5)}
     T.tnc_destroy(ctx)
-    # the oracle on a sample of about cpu_seconds
+    cpu = cpu_baseline_codec(cpu_seconds)
+    best = max(out.values(), key=lambda v: v["quantize_gbs"])
+    return {"metric": "exchange codec throughput (quantize + dequantize of a complex64 tensor)",
+            "value": round(min(v["quantize_gbs"] for v in out.values()), 1), "unit": "GB/s",
+            "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"2^{n_entries.bit_length() - 1}-entry complex64 tensor (2^{n.bit_length() - 1} "
+                                   f"float32 values), N(0,1) values"},
+            "kinds": out,
+            "roofline": {"bound": "hbm", "peak": HBM_GBS, "unit": "GB/s",
+                         "frac_best": round(best["quantize_gbs"] / HBM_GBS, 4)},
+            "cpu_baseline": cpu}
+
+
+def compression_rate(T, kind, n_reals, group=0):
+    """Eq. compress from the library's own code and group sizes: (scales +
+    zeros + codes) / the float32 bytes of the tensor."""
+    cb, ng = T.tnc_quant_sizes(kind, n_reals, group)
+    return (8.0 * ng + cb) / (4.0 * n_reals)
+
+
+def codec_study(torch, T, cn, workloads, n_steps=8):
+    """Single-step quantization (Sec. 4.3.1) on the 30-qubit path: the result of
+    one of its largest steps goes through the codec on every slice, and the
+    complex64 amplitudes are compared with the stored oracle amplitudes; the
+    relative fidelity is the quantized run's fidelity over the plain run's."""
+    w = setup_30q(None, T, cn, workloads)
+    ws = torch.empty(64 << 30, dtype=torch.uint8, device="cuda:0")
+    ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    plan = T.tnc_plan_create(ctx, w["net"], w["ssa"], w["sliced"], w["open_q"], "c64")
+    n = T.tnc_plan_info(plan)["n_steps"]
+    steps = T.tnc_plan_steps(plan, n)
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "config2_amplitudes.npy"))
+    total = 1 << len(w["sliced"])
+
+    def fid(o):
+        return float(abs(np.vdot(ref, o)) ** 2 / (np.vdot(ref, ref).real * np.vdot(o, o).real))
+
+    base, _ = T.tnc_execute(plan, w["bits"], 0, total)
+    f_c64 = fid(base)
+    mnkb = steps["log2_mnkb"]
+    rank = [int(mnkb[i][3] + mnkb[i][0] + mnkb[i][1]) for i in range(n)]   # log2 entries of the result
+    pick = sorted(sorted(range(n), key=lambda i: (rank[i], i))[-n_steps:])
+    rows = []
+    for i in pick:
+        row = {"step": i, "log2_entries": rank[i], "slice_dependent": bool(steps["dep"][i])}
+        for kind in ("half", "int8", "int4"):
+            T.tnc_plan_set_codec(plan, i, kind, 0)
+            o, _ = T.tnc_execute(plan, w["bits"], 0, total)
+            row[kind] = {"relative_fidelity": round(fid(o) / f_c64, 9),
+                         "compression_rate": round(compression_rate(T, kind, 2 << rank[i]), 5)}
+        rows.append(row)
+        log(f"step {i}: 2^{rank[i]} entries, " + ", ".join(f"{k} {row[k]['relative_fidelity']:.6f}"
+                                                        for k in ("half", "int8", "int4")))
+    T.tnc_plan_set_codec(plan, -1, "half", 0)
+    T.tnc_plan_destroy(plan)
+    T.tnc_network_destroy(w["net"])
+    T.tnc_destroy(ctx)
+    return {"study": "single-step quantization, relative fidelity (quantized / complex64, both against the "
+                     "stored FP64 oracle amplitudes)",
+            "workload": w["label"], "complex64_fidelity": f_c64, "steps": rows}
+
+
+def cpu_baseline_codec(cpu_seconds):
+    """The oracle's numpy codec on a bounded sample (float32 decisions)."""
+    from oracle import codec as ocodec
     xs = np.random.default_rng(0).normal(size=1 << 22).astype(np.float32)
     t0 = time.perf_counter()
     reps_cpu = 0
@@ -228,19 +291,10 @@ def codec_bench(torch, T, n_entries=1 << 27, reps=5, cpu_seconds=10.0):
         reps_cpu += 1
     dt = time.perf_counter() - t0
     cpu_rate = 3 * reps_cpu * xs.size * 4 / dt / 1e9
-    best = max(out.values(), key=lambda v: v["quantize_gbs"])
-    return {"metric": "exchange codec throughput (quantize + dequantize of a complex64 tensor)",
-            "value": round(min(v["quantize_gbs"] for v in out.values()), 1), "unit": "GB/s",
-            "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-            "config": {"workload": f"2^{n_entries.bit_length() - 1}-entry complex64 tensor (2^{n.bit_length() - 1} "
-                                   f"float32 values), N(0,1) values"},
-            "kinds": out,
-            "roofline": {"bound": "hbm", "peak": HBM_GBS, "unit": "GB/s",
-                         "frac_best": round(best["quantize_gbs"] / HBM_GBS, 4)},
-            "cpu_baseline": {"value": round(cpu_rate, 4), "unit": "GB/s of float32 input (quantize + dequantize)",
-                             "cores": 1, "kind": "oracle",
-                             "sample": f"oracle codec (numpy, float32 decisions) on 2^22 values, all three kinds, "
-                                       f"{reps_cpu} rounds in {dt:.1f} s"}}
+    return {"value": round(cpu_rate, 4), "unit": "GB/s of float32 input (quantize + dequantize)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"oracle codec (numpy, float32 decisions) on 2^22 values, all three kinds, "
+                      f"{reps_cpu} rounds in {dt:.1f} s"}
 
 
 def roofline_entry(fam, dtype_key):
@@ -325,6 +379,8 @@ def main():
                     help="only run a 1 GiB device copy 4 times (reference for the HBM byte counters)")
     ap.add_argument("--codec", action="store_true",
                     help="only measure the low-precision exchange codec (its own JSON line)")
+    ap.add_argument("--codec-study", action="store_true",
+                    help="only run the single-step quantization study on the 30-qubit path (its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): slice blocks on several GPUs "
@@ -340,6 +396,10 @@ def main():
     from paper_2407_00769_amd import _tnc as T
     if args.codec:
         print(json.dumps(codec_bench(torch, T)), flush=True)
+        return
+    if args.codec_study:
+        from paper_2407_00769_amd import circuit_network as cn
+        print(json.dumps(codec_study(torch, T, cn, workloads)), flush=True)
         return
     from paper_2407_00769_amd import circuit_network as cn
 
