@@ -18,4 +18,8 @@ Contents, each a plain and slow definition:
 * ``metrics``     -- fidelity (paper Eq. ``fidelity``), relative errors,
                      linear XEB and Porter-Thomas distance.
 * ``mlp``         -- FP64 forward/backward/Adam of the step-cost MLP.
+* ``codec``       -- the low-precision exchange codec (paper Sec. 3.2,
+                     Eq. ``quantcal``, Table ``quanttable``, Eq. ``compress``).
+* ``postselect``  -- top-k post-selection in a correlated subspace and the
+                     linear XEB of the kept samples (paper Sec. 1 and 2.3).
 """
