@@ -101,6 +101,10 @@ struct GemmShape {
     // pairs) and a second kernel sums the parts in order
     int64_t split = 1;
     float2 *part = nullptr;
+    // the split factor is chosen for this many slices per launch, the count
+    // the partial buffer was sized for (0: the launch's own count); a launch
+    // over fewer slices keeps that factor, so it never needs more buffer
+    int64_t split_slices = 0;
 };
 
 // Scale bookkeeping of the 16-bit forms, per tensor and slice.

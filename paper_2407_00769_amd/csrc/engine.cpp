@@ -399,6 +399,7 @@ double autotune_plan(tnc_plan *p) {
         g.sC = nz;
         g.part = p->d_part;
         const int Sl = rec.dep ? p->S : 1;
+        g.split_slices = Sl;
         std::vector<int> cands;
         // big steps: only the large matrix-core tiles are worth timing
         const bool big = rec.flops * (double)Sl > 1e13;
@@ -576,6 +577,7 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
     g.sB = B.dep ? nbb : 0;
     g.sC = nz;
     g.part = p->d_part;
+    g.split_slices = rec.dep ? p->S : 1;   // the slice count d_part was sized for
     (void)es;
     ScaleRefs sc{};
     if (dt != Dtype::C64) {

@@ -1541,7 +1541,9 @@ void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void 
     const ScaleRefs &s = sc ? *sc : none;
     if (dt != Dtype::C64 && !sc) TNC_THROW(TNC_EINVAL, "16-bit forms need scale bookkeeping");
     GemmShape g = g_in;
-    g.split = g.part ? splitk_factor(kid, dt, al, g, S) : 1;
+    const int64_t split_s = g.split_slices > 0 ? g.split_slices : S;
+    if (S > split_s) TNC_THROW(TNC_EINVAL, "launch covers more slices than its split-K buffer was sized for");
+    g.split = g.part ? splitk_factor(kid, dt, al, g, (int)split_s) : 1;
     if (g.split > 1) {
         if (dt == Dtype::C64)
             launch_c64(kid, A, B, C, g, S, st);

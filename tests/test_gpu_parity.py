@@ -351,6 +351,10 @@ def test_config2_full_block_matches_oracle(T, ctx, prec):
         assert f >= 0.999 and rl <= 0.05, (f, rl)
     else:
         assert f >= 0.99, (f, rl)
+    # partial blocks: a group of fewer slices than the plan holds in flight
+    # keeps the split-K factor its partial-sum buffer was sized for
+    parts = [T.tnc_execute(plan, bits, a, b)[0] for a, b in ((0, 16), (16, 20), (20, 21), (21, 256))]
+    np.testing.assert_allclose(sum(parts), out, rtol=0, atol=1e-12 * np.max(np.abs(out)))
     T.tnc_plan_destroy(plan)
     T.tnc_destroy(big)
     T.tnc_network_destroy(net)
