@@ -278,6 +278,54 @@ def codec_study(torch, T, cn, workloads, n_steps=8):
             "workload": w["label"], "complex64_fidelity": f_c64, "steps": rows}
 
 
+def postselect_study(torch, T, cn, workloads, n_sub=16, fractions=(1 / 64, 1 / 16, 1 / 4, 1.0)):
+    """Top-1 post-selection per correlated subspace (Sec. 1 and 2.3) on the
+    30-qubit path: the FP16-4M plan contracts a fraction of the 256 slices of
+    each subspace (1024 bitstrings, open qubits 20-29, a seeded 20-bit prefix),
+    tnc_topk keeps its most probable bitstring, and the linear XEB of the kept
+    samples is taken under the complex64 run of all slices."""
+    w = setup_30q(None, T, cn, workloads)
+    ws = torch.empty(64 << 30, dtype=torch.uint8, device="cuda:0")
+    ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    p64 = T.tnc_plan_create(ctx, w["net"], w["ssa"], w["sliced"], w["open_q"], "c64")
+    p16 = T.tnc_plan_create(ctx, w["net"], w["ssa"], w["sliced"], w["open_q"], "f16_4m")
+    total = 1 << len(w["sliced"])
+    kept = {f: [] for f in fractions}
+    fids = {f: [] for f in fractions}
+    secs = {f: 0.0 for f in fractions}
+    first, topk_ms = [], []
+    for seed in range(n_sub):
+        bits = workloads.subspace_bitstrings(30, w["open_q"], 100 + seed)
+        ideal, _ = T.tnc_execute(p64, bits, 0, total)
+        pi = ideal.real ** 2 + ideal.imag ** 2
+        first.append(pi[0])
+        for f in fractions:
+            ns = max(1, int(round(total * f)))
+            t0 = time.perf_counter()
+            approx, _ = T.tnc_execute(p16, bits, 0, ns)
+            secs[f] += time.perf_counter() - t0
+            idx, _prob, ms = T.tnc_topk(ctx, torch.from_numpy(np.ascontiguousarray(approx)).to("cuda:0"), 1)
+            topk_ms.append(ms)
+            kept[f].append(pi[int(idx[0])])
+            fids[f].append(float(abs(np.vdot(ideal, approx)) ** 2 / (np.vdot(ideal, ideal).real *
+                                                                     np.vdot(approx, approx).real)))
+    T.tnc_plan_destroy(p64)
+    T.tnc_plan_destroy(p16)
+    T.tnc_network_destroy(w["net"])
+    T.tnc_destroy(ctx)
+    n_bits = 1 << len(w["open_q"])
+    harmonic = float(np.sum(1.0 / np.arange(1, n_bits + 1)))
+    rows = [{"slice_fraction": f, "slices": max(1, int(round(total * f))),
+             "mean_fidelity": round(float(np.mean(fids[f])), 6),
+             "xeb_top1": round(float(2.0 ** 30 * np.mean(kept[f]) - 1.0), 4),
+             "seconds_per_subspace": round(secs[f] / n_sub, 5)} for f in fractions]
+    return {"study": "top-1 post-selection per correlated subspace, linear XEB of the kept samples",
+            "workload": w["label"], "subspaces": n_sub, "bitstrings_per_subspace": n_bits,
+            "xeb_fixed_pick": round(float(2.0 ** 30 * np.mean(first) - 1.0), 4),
+            "xeb_top1_expected_exact": round(harmonic - 1.0, 4),
+            "topk_ms_mean": round(float(np.mean(topk_ms)), 4), "rows": rows}
+
+
 def cpu_baseline_codec(cpu_seconds):
     """The oracle's numpy codec on a bounded sample (float32 decisions)."""
     from oracle import codec as ocodec
@@ -381,6 +429,8 @@ def main():
                     help="only measure the low-precision exchange codec (its own JSON line)")
     ap.add_argument("--codec-study", action="store_true",
                     help="only run the single-step quantization study on the 30-qubit path (its own JSON line)")
+    ap.add_argument("--postselect", action="store_true",
+                    help="only run the top-1 post-selection study on the 30-qubit path (its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): slice blocks on several GPUs "
@@ -396,6 +446,10 @@ def main():
     from paper_2407_00769_amd import _tnc as T
     if args.codec:
         print(json.dumps(codec_bench(torch, T)), flush=True)
+        return
+    if args.postselect:
+        from paper_2407_00769_amd import circuit_network as cn
+        print(json.dumps(postselect_study(torch, T, cn, workloads)), flush=True)
         return
     if args.codec_study:
         from paper_2407_00769_amd import circuit_network as cn

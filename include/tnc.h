@@ -318,6 +318,25 @@ int tnc_dequantize(tnc_ctx *ctx, int32_t kind, int64_t n, const void *codes, con
  * The plan allocates the code buffers.  TNC_EUNSUPPORTED for 16-bit plans. */
 int tnc_plan_set_codec(tnc_plan *plan, int32_t step, int32_t kind, int32_t group);
 
+/* ------------------------------------------------------------------ post-selection
+ * Top-k post-selection in a correlated subspace (paper Sec. 1 and Sec. 2.3,
+ * post-processing): of the n amplitudes of one subspace, the k bitstrings with
+ * the largest probabilities.
+ *
+ * amps:     device, n complex128 amplitudes (interleaved re, im; the layout
+ *           tnc_execute returns), 8-byte aligned, all finite.
+ * k:        1..1024; min(k, n) entries are written.
+ * idx_out:  device, int64 positions into amps, most probable first.
+ * prob_out: device, float64 probabilities re*re + im*im (each operation
+ *           rounded on its own) of those entries.
+ * Order: probability descending, then position ascending, so the list is
+ * unique even with ties.  The context's workspace holds the candidate rounds
+ * (32 bytes x ceil(n / 2048) x k when n > 2048; TNC_ENOMEM if it is smaller).
+ * Runs on the context's stream and waits for it; ms_out (optional) = device
+ * time.  TNC_EINVAL on a NULL or misaligned buffer or k out of range. */
+int tnc_topk(tnc_ctx *ctx, int64_t n, const double *amps, int32_t k, int64_t *idx_out, double *prob_out,
+             double *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,7 @@ _SIGS = {
     "tnc_dequantize": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp,
                                       c_double_p]),
     "tnc_plan_set_codec": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "tnc_topk": (ctypes.c_int, [vp, ctypes.c_int64, vp, ctypes.c_int32, vp, vp, c_double_p]),
     "tnc_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int32]),
     "tnc_plan_step_times": (ctypes.c_int, [vp, ctypes.c_int32, c_double_p, c_double_p, c_int32_p]),
     "tnc_plan_steps": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, c_int32_p, c_int32_p, c_int32_p, c_double_p,
@@ -402,3 +403,20 @@ def tnc_dequantize(ctx, kind, n, codes, scales, zeros, group=0):
 
 def tnc_plan_set_codec(plan, step, kind="int4", group=0):
     _check(lib.tnc_plan_set_codec(plan, int(step), QKINDS.get(kind, kind), int(group)))
+
+
+def tnc_topk(ctx, amps, k):
+    """Top-k post-selection of device complex128 amplitudes (a torch tensor on
+    the context's device); returns (indices, probabilities, ms) as torch
+    tensors on that device."""
+    import torch
+    assert amps.dtype == torch.complex128 and amps.is_contiguous()
+    n = amps.numel()
+    kk = min(int(k), n)
+    idx = torch.empty(max(kk, 1), dtype=torch.int64, device=amps.device)
+    prob = torch.empty(max(kk, 1), dtype=torch.float64, device=amps.device)
+    ms = ctypes.c_double(0.0)
+    torch.cuda.synchronize(amps.device)
+    _check(lib.tnc_topk(ctx, n, ctypes.c_void_p(amps.data_ptr()), int(k), ctypes.c_void_p(idx.data_ptr()),
+                        ctypes.c_void_p(prob.data_ptr()), ctypes.byref(ms)))
+    return idx[:kk], prob[:kk], ms.value

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtnc.so")
 SOURCES = ["kernels.hip", "gemm.hip", "mlp.hip", "codec.hip", "planner.cpp", "engine.cpp", "contract.cpp",
-           "search.cpp", "codec.cpp"]
+           "search.cpp", "codec.cpp", "postselect.hip", "postselect.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -22,9 +22,10 @@ FLAGS = [
 ]
 
 
-# the codec takes its integer decisions with every float32 operation rounded
-# on its own: no contraction into fused multiply-adds there
-EXTRA = {"codec.hip": ["-ffp-contract=off"]}
+# the codec takes its integer decisions, and the post-selection its
+# probabilities, with every operation rounded on its own: no contraction into
+# fused multiply-adds there
+EXTRA = {"codec.hip": ["-ffp-contract=off"], "postselect.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:
