@@ -120,3 +120,13 @@ def test_planner_flops_match_label_count():
     info = T.tnc_plan_analyze(net, ssa, sl, open_q, "f16_4m")
     want = _einsum_flops([t.labels for t in st.tensors], list(ssa), st.output_labels)
     assert info["flops_per_slice"] + info["flops_invariant"] == pytest.approx(want, rel=1e-12)
+
+
+def test_smoke_case_is_sliced_under_its_cap():
+    """The host half of the smoke run finds a sliced path under its cap."""
+    import __graft_entry__ as ge
+    from paper_2407_00769_amd import _tnc as T
+    c, net, ssa, sl, open_q, bits = ge.smoke_case()
+    assert len(sl) > 0 and len(ssa) == 2 * (T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")["n_steps"])
+    assert T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")["max_rank"] <= 8
+    T.tnc_network_destroy(net)
