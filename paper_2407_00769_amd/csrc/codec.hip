@@ -122,13 +122,18 @@ __global__ void __launch_bounds__(256) minmax_partial_kernel(const float *__rest
     }
 }
 
+// one wave: the extremes of the partials (min and max are exact in any order)
 __global__ void scale_zero_kernel(const float2 *__restrict__ part, int np, int kind, float *scales, float *zeros) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     float mn = FLT_MAX, mx = -FLT_MAX;
-    for (int i = 0; i < np; i++) {
+    for (int i = threadIdx.x; i < np; i += 64) {
         mn = fminf(mn, part[i].x);
         mx = fmaxf(mx, part[i].y);
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, o, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    if (threadIdx.x != 0) return;
     const QKind k = qkind(kind);
     float s, z;
     scale_zero(k, qpow(mn, k.exp), qpow(mx, k.exp), s, z);
