@@ -403,7 +403,8 @@ double autotune_plan(tnc_plan *p) {
         std::vector<int> cands;
         // big steps: only the large matrix-core tiles are worth timing
         const bool big = rec.flops * (double)Sl > 1e13;
-        static const int big_order[] = {K_DMA_8, K_DMA_8W, K_DMA_4, K_DMA_2, K_DMA_N64, K_DMA_N32, K_MFMA_XL, K_MFMA_L2, K_MFMA_L};
+        static const int big_order[] = {K_DMA_8,   K_DMA_8W,  K_DMA_4,   K_DMA_2,   K_DMA_N64, K_DMA_N32,
+                                        K_DMA3_N64, K_DMA3_2, K_MFMA_XL, K_MFMA_L2, K_MFMA_L};
         if (big) {
             for (int k : big_order)
                 if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);

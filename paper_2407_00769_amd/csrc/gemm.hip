@@ -829,8 +829,40 @@ template <int VM_AHEAD, int LPT> __device__ __forceinline__ void ring_wait_for(i
     }
 }
 
-template <bool BF, int BM, int BN, int WM, int WN, int STAGES>
-__global__ void __launch_bounds__(64 * WM * WN, (STAGES == 2 ? 2 : 1))
+// blocks per CU the register budget is sized for: two-stage tiles fit two
+// blocks in LDS, except the 3M 128 x 128 tile, whose 64 x 64 wave tiles need
+// three accumulator sets (192 registers) and so run one wave per SIMD
+template <bool M3, int BM, int BN, int STAGES> constexpr int dma_min_blocks() {
+    return (STAGES == 2 && !(M3 && BM == 128 && BN == 128)) ? 2 : 1;
+}
+
+// 3M from the same ring: a k-step covers 16 complex k; lane l's two chunks
+// hold complex k 8(l/32)..+7 of its row as 8 words (re low, im high).  One
+// byte permute per pair of words gives the real plane, one the imaginary
+// plane, and a packed FP16 add their rounded sum:
+//     T1 = Ar Br,  T2 = Ai Bi,  T3 = (Ar + Ai)(Br + Bi);  Re C = T1 - T2,  Im C = T3 - T1 - T2.
+__device__ __forceinline__ void planes3m(const u32x4 &w0, const u32x4 &w1, u32x4 &re, u32x4 &im, u32x4 &sm) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    re[0] = __builtin_amdgcn_perm(w0[1], w0[0], 0x05040100u);
+    re[1] = __builtin_amdgcn_perm(w0[3], w0[2], 0x05040100u);
+    re[2] = __builtin_amdgcn_perm(w1[1], w1[0], 0x05040100u);
+    re[3] = __builtin_amdgcn_perm(w1[3], w1[2], 0x05040100u);
+    im[0] = __builtin_amdgcn_perm(w0[1], w0[0], 0x07060302u);
+    im[1] = __builtin_amdgcn_perm(w0[3], w0[2], 0x07060302u);
+    im[2] = __builtin_amdgcn_perm(w1[1], w1[0], 0x07060302u);
+    im[3] = __builtin_amdgcn_perm(w1[3], w1[2], 0x07060302u);
+    // (the vector elements are copied to scalars first: a bit cast straight from
+    // an element of an ext_vector was compiled as a cast of element 0)
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint32_t r = re[q], i = im[q];
+        const h2 sum = __builtin_bit_cast(h2, r) + __builtin_bit_cast(h2, i);
+        sm[q] = __builtin_bit_cast(uint32_t, sum);
+    }
+}
+
+template <bool BF, bool M3, int BM, int BN, int WM, int WN, int STAGES>
+__global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAGES>()))
     gemm_dma_h_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t *__restrict__ C,
                       GemmShape g, ScaleRefs sc) {
     using Tl = DTile<BM, BN, WM, WN, STAGES>;
@@ -893,13 +925,26 @@ __global__ void __launch_bounds__(64 * WM * WN, (STAGES == 2 ? 2 : 1))
                                              16, 0, 0);
     };
 
-    floatx16 acc[FM][FC][2];
+    static_assert(!(M3 && BF), "the DMA 3M path is FP16 only");
+    constexpr int NACC = M3 ? 3 : 2;
+    floatx16 acc[FM][FC][NACC];
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
         for (int j = 0; j < FC; j++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) acc[i][j][0][r] = acc[i][j][1][r] = 0.f;
+            for (int a = 0; a < NACC; a++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) acc[i][j][a][r] = 0.f;
+    // the complex result entry r of block (i, j)
+    auto c_re = [&](int i, int j, int r) {
+        if constexpr (M3) return acc[i][j][0][r] - acc[i][j][1][r];
+        else return acc[i][j][0][r];
+    };
+    auto c_im = [&](int i, int j, int r) {
+        if constexpr (M3) return acc[i][j][2][r] - acc[i][j][0][r] - acc[i][j][1][r];
+        else return acc[i][j][1][r];
+    };
 
     // fragment rows: wm*WTM + 32i + lane%32 (A) and wn*WTC + 32j + lane%32
     // (B); both have row & 7 = lane & 7, so the slot of chunk 2kk + lane/32
@@ -942,10 +987,50 @@ __global__ void __launch_bounds__(64 * WM * WN, (STAGES == 2 ? 2 : 1))
 #pragma unroll
     for (int st = 0; st < STAGES - 1; st++)
         if (st < nk) issue(st);
+    // 3M chunk offsets within a stage: step ks, chunk h2 of lane l's pair
+    int a3_off[2][2], b3_off[2][2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+        for (int h2 = 0; h2 < 2; h2++) {
+            const int slot = ((4 * ks + 2 * (lane >> 5) + h2) ^ (lane & 7)) * 16;
+            a3_off[ks][h2] = (wm * WTM + (lane & 31)) * 128 + slot;
+            b3_off[ks][h2] = Tl::A_BYTES + (wn * WTC + (lane & 31)) * 128 + slot;
+        }
+    auto step3 = [&](const uint8_t *sb, int ks) {
+        u32x4 ar[FM], ai[FM], as[FM], br[FC], bi[FC], bs[FC];
+#pragma unroll
+        for (int i = 0; i < FM; i++) {
+            const u32x4 w0 = *(const u32x4 *)(sb + a3_off[ks][0] + i * 32 * 128);
+            const u32x4 w1 = *(const u32x4 *)(sb + a3_off[ks][1] + i * 32 * 128);
+            planes3m(w0, w1, ar[i], ai[i], as[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < FC; j++) {
+            const u32x4 w0 = *(const u32x4 *)(sb + b3_off[ks][0] + j * 32 * 128);
+            const u32x4 w1 = *(const u32x4 *)(sb + b3_off[ks][1] + j * 32 * 128);
+            planes3m(w0, w1, br[j], bi[j], bs[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < FC; j++)
+#pragma unroll
+            for (int i = 0; i < FM; i++) {
+                acc[i][j][0] = mfma16<false>(ar[i], br[j], acc[i][j][0]);
+                acc[i][j][1] = mfma16<false>(ai[i], bi[j], acc[i][j][1]);
+                acc[i][j][2] = mfma16<false>(as[i], bs[j], acc[i][j][2]);
+            }
+    };
+
     for (int kt = 0; kt < nk; kt++) {
         ring_wait_for<STAGES - 2, Tl::LPT>(nk - 1 - kt);
         if (kt + STAGES - 1 < nk) issue(kt + STAGES - 1);
         const uint8_t *sb = smem + (kt % STAGES) * Tl::STAGE_BYTES;
+        if constexpr (M3) {
+            step3(sb, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            step3(sb, 1);
+            continue;
+        }
         // Two register sets of fragments: the reads of step kk+1 are issued
         // before the matrix-core work of step kk, and a set's first use (its
         // B transform) comes before the next reads, so each wait covers only
@@ -986,7 +1071,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (STAGES == 2 ? 2 : 1))
                 for (int r = 0; r < 16; r++) {
                     int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                     int col = wn * WTC + j * 32 + (lane & 31);
-                    pp[(m0 + row) * g.N + n0 + col] = make_float2(acc[i][j][0][r], acc[i][j][1][r]);
+                    pp[(m0 + row) * g.N + n0 + col] = make_float2(c_re(i, j, r), c_im(i, j, r));
                 }
         return;
     }
@@ -1000,7 +1085,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (STAGES == 2 ? 2 : 1))
             for (int r = 0; r < 16; r++) {
                 int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 int col = wn * WTC + j * 32 + (lane & 31);
-                Cw[row * BN + col] = Pack<W>::make(acc[i][j][0][r] * scale, acc[i][j][1][r] * scale).w;
+                Cw[row * BN + col] = Pack<W>::make(c_re(i, j, r) * scale, c_im(i, j, r) * scale).w;
             }
     __syncthreads();
     float mx = 0.f;
@@ -1281,6 +1366,8 @@ const char *kernel_name(int k) {
         case K_DMA_2: return "dma_2";
         case K_DMA_N64: return "dma_n64";
         case K_DMA_N32: return "dma_n32";
+        case K_DMA3_N64: return "dma3_n64";
+        case K_DMA3_2: return "dma3_2";
         default: return "?";
     }
 }
@@ -1322,6 +1409,8 @@ static TileCfg tile_of(int kid, Dtype dt, Algo al) {
             case K_MFMA_W: return {256, 32};
             case K_MFMA_XL: return {256, 64};
             case K_MFMA_L2: return {128, 32};
+            case K_DMA3_N64: return {256, 64};
+            case K_DMA3_2: return {128, 128};
         }
     }
     return {0, 0};
@@ -1340,6 +1429,11 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
     if (kid >= K_DMA_4 && kid <= K_DMA_N32) {
         // 16-bit 4M, both operands chunked along k, whole tiles and k-tiles
         if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
+        if (g.K % 32) return false;
+    }
+    if (kid == K_DMA3_N64 || kid == K_DMA3_2) {
+        // FP16 3M, the same operand conditions
+        if (dt != Dtype::F16 || al != Algo::M3 || !g.a_kc || !g.b_kc) return false;
         if (g.K % 32) return false;
     }
     TileCfg t = tile_of(kid, dt, al);
@@ -1444,11 +1538,11 @@ static void launch_h_cfg(const void *A, const void *B, void *C, const GemmShape 
                        (uint32_t *)C, g, sc);
 }
 
-template <bool BF, int BM, int BN, int WM, int WN, int STAGES>
+template <bool BF, int BM, int BN, int WM, int WN, int STAGES, bool M3 = false>
 static void launch_dma_cfg(const void *A, const void *B, void *C, const GemmShape &g, int S, const ScaleRefs &sc,
                            hipStream_t st) {
     using Tl = DTile<BM, BN, WM, WN, STAGES>;
-    auto kern = gemm_dma_h_kernel<BF, BM, BN, WM, WN, STAGES>;
+    auto kern = gemm_dma_h_kernel<BF, M3, BM, BN, WM, WN, STAGES>;
     static bool attr = false;
     if (!attr) {
         HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, Tl::LDS_BYTES));
@@ -1469,6 +1563,10 @@ static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, co
     if (kid == K_DMA_2) return launch_dma_cfg<BF, 128, 128, 2, 2, 2>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_N64) return launch_dma_cfg<BF, 256, 64, 4, 2, 2>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_N32) return launch_dma_cfg<BF, 256, 32, 4, 1, 2>(A, B, C, g, S, sc, st);
+    if constexpr (!BF) {
+        if (kid == K_DMA3_N64) return launch_dma_cfg<false, 256, 64, 4, 2, 2, true>(A, B, C, g, S, sc, st);
+        if (kid == K_DMA3_2) return launch_dma_cfg<false, 128, 128, 2, 2, 2, true>(A, B, C, g, S, sc, st);
+    }
     if (al == Algo::M4) {
         switch (kid) {
             case K_MFMA_S: launch_h_cfg<BF, false, 64, 16, 32, 2, 1>(A, B, C, g, S, sc, st); break;

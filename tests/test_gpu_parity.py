@@ -102,7 +102,8 @@ def _check_contract(T, ctx, prec, nb, m, n, k, seed, scale_log2=0):
 
 
 KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5, "mfma_xl": 6,
-           "mfma_l2": 7, "dma_4": 8, "dma_8": 9, "dma_8w": 10, "dma_2": 11, "dma_n64": 12, "dma_n32": 13}
+           "mfma_l2": 7, "dma_4": 8, "dma_8": 9, "dma_8w": 10, "dma_2": 11, "dma_n64": 12, "dma_n32": 13,
+           "dma3_n64": 14, "dma3_2": 15}
 SHAPES = [  # nb, m, n, k  (log2)
     (0, 9, 6, 5), (1, 8, 5, 3), (0, 10, 4, 6), (2, 7, 7, 4), (0, 8, 0, 2), (0, 6, 3, 0), (0, 12, 5, 7),
     (0, 9, 8, 6), (1, 8, 7, 5),
@@ -160,7 +161,8 @@ def test_contract_orientations(T, ctx, prec, kname, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("kname", ["skinny", "mfma_m", "mfma_xl", "mfma_l2", "dma_4", "dma_8", "dma_8w", "dma_2", "dma_n64", "dma_n32"])
+@pytest.mark.parametrize("kname", ["skinny", "mfma_m", "mfma_xl", "mfma_l2", "dma_4", "dma_8", "dma_8w", "dma_2", "dma_n64", "dma_n32",
+                                   "dma3_n64", "dma3_2"])
 def test_contract_split_layouts(T, ctx, prec, kname, monkeypatch):
     # operands and result whose GEMM indices lie in two runs each (A as
     # [m_hi][k_hi][m_lo][k_lo], B as [k_hi][n][k_lo], C as [m_hi][n_hi][m_lo][n_lo])
