@@ -434,7 +434,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): slice blocks on several GPUs "
-              f"would be independent ranges summed by one all-reduce, which this build does not launch",
+              f"would be independent ranges summed by one all-reduce, which this program does not launch",
               file=sys.stderr)
         sys.exit(2)
 
