@@ -130,3 +130,43 @@ def test_smoke_case_is_sliced_under_its_cap():
     assert len(sl) > 0 and len(ssa) == 2 * (T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")["n_steps"])
     assert T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")["max_rank"] <= 8
     T.tnc_network_destroy(net)
+
+
+def test_codec_sizes_and_group_rules():
+    """Code and group counts of the exchange codec (Sec. 3.2): half 2 bytes and
+    int8 1 byte per value in one group; int4 two values per byte in groups of a
+    power of two from 16 to 1024 (128 by default); anything else is refused."""
+    n = 1000
+    assert T.tnc_quant_sizes("half", n) == (2 * n, 1)
+    assert T.tnc_quant_sizes("int8", n) == (n, 1)
+    assert T.tnc_quant_sizes("int4", n) == ((n + 1) // 2, (n + 127) // 128)
+    assert T.tnc_quant_sizes("int4", n, 16) == ((n + 1) // 2, (n + 15) // 16)
+    assert T.tnc_quant_sizes("int4", 0) == (0, 0)
+    for kind, group in (("int4", 100), ("int4", 2048), ("int4", 8), ("half", 64), ("int8", 128)):
+        with pytest.raises(T.TncError):
+            T.tnc_quant_sizes(kind, n, group)
+    with pytest.raises(T.TncError):
+        T.tnc_quant_sizes(7, n)
+
+
+def test_search_is_deterministic_per_seed():
+    c, st, net, nt = _net(2)
+    open_q = list(range(20, 30))
+    a = T.tnc_search(net, nt, open_q, 24, restarts=4, seed=5)
+    b = T.tnc_search(net, nt, open_q, 24, restarts=4, seed=5)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    T.tnc_network_destroy(net)
+
+
+def test_slice_path_meets_a_lower_cap():
+    """Slicing a found path further (extra sliced labels) brings its largest
+    per-slice tensor under a tighter cap, and keeps labels already sliced."""
+    c, st, net, nt = _net(2)
+    open_q = list(range(20, 30))
+    ssa, sl, _ = T.tnc_search(net, nt, open_q, 24, restarts=4, seed=1)
+    before = T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")["max_rank"]
+    more = T.tnc_slice_path(net, ssa, open_q, before - 2, sliced_in=list(sl))
+    assert set(sl) <= set(more.tolist()) and len(more) > len(sl)
+    assert T.tnc_plan_analyze(net, ssa, more, open_q, "c64")["max_rank"] <= before - 2
+    T.tnc_network_destroy(net)
