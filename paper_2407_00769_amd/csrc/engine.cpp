@@ -805,11 +805,11 @@ extern "C" int tnc_execute(tnc_plan *p, int64_t n_bitstrings, const uint64_t *bi
         for (int j = 0; j < ro; j++) {
             int l = orig[j];
             if (an.fixed[l] == 1) {
-                int q = an.open_qubit_of_label.size() ? -1 : -1;
-                // find the qubit of this output label
+                // a closed output label: the value of its qubit selects the half
+                int q = -1;
                 for (int qq : p->closed_qubits)
                     if (p->output_labels[qq] == l) q = qq;
-                if (closed_val[q]) off += (int64_t)1 << (ro - 1 - j);
+                if (q >= 0 && closed_val[q]) off += (int64_t)1 << (ro - 1 - j);
             }
         }
         if (off != p->closed_state[i]) {
