@@ -188,37 +188,43 @@ __global__ void __launch_bounds__(256) quantize_whole_kernel(const float *__rest
     }
 }
 
+// Chunks of 4 values, lane-contiguous: in each of a thread's four rounds the
+// 64 lanes of a wave decode 64 consecutive chunks, so every 16-byte store
+// instruction writes one contiguous 1 KB run.
 template <int KIND>
 __global__ void __launch_bounds__(256) dequantize_whole_kernel(const void *__restrict__ codes, int64_t n,
                                                                const float *__restrict__ scales,
                                                                const float *__restrict__ zeros, float *__restrict__ x) {
     const QKind k = qkind(KIND);
     const float scale = scales[0], zero = zeros[0];
-    const int64_t n16 = n / 16;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n16; t += (int64_t)gridDim.x * blockDim.x) {
-        float v[16];
-        if constexpr (KIND == 0) {
-            const uint4 *c = (const uint4 *)codes + 2 * t;
-            uint4 a = c[0], b = c[1];
-            uint32_t h[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    const int64_t n4 = n / 4, step = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x; c0 < n4; c0 += step) {
+        float v[4][4];
 #pragma unroll
-            for (int i = 0; i < 8; i++) {
-                v[2 * i] = __half2float(__ushort_as_half((unsigned short)(h[i] & 0xffffu)));
-                v[2 * i + 1] = __half2float(__ushort_as_half((unsigned short)(h[i] >> 16)));
+        for (int u = 0; u < 4; u++) {
+            const int64_t c = c0 + (int64_t)u * blockDim.x;
+            if (c >= n4) break;
+            if constexpr (KIND == 0) {
+                const uint2 h = ((const uint2 *)codes)[c];
+                v[u][0] = __half2float(__ushort_as_half((unsigned short)(h.x & 0xffffu)));
+                v[u][1] = __half2float(__ushort_as_half((unsigned short)(h.x >> 16)));
+                v[u][2] = __half2float(__ushort_as_half((unsigned short)(h.y & 0xffffu)));
+                v[u][3] = __half2float(__ushort_as_half((unsigned short)(h.y >> 16)));
+            } else {
+                const uint32_t b = ((const uint32_t *)codes)[c];
+#pragma unroll
+                for (int i = 0; i < 4; i++) v[u][i] = (float)(int8_t)((b >> (8 * i)) & 0xffu);
             }
-        } else {
-            uint4 a = ((const uint4 *)codes)[t];
-            uint32_t b[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-            for (int i = 0; i < 16; i++) v[i] = (float)(int8_t)((b[i / 4] >> (8 * (i % 4))) & 0xffu);
         }
 #pragma unroll
-        for (int c = 0; c < 4; c++)
-            ((float4 *)x)[4 * t + c] = make_float4(qdecode(k, v[4 * c], scale, zero), qdecode(k, v[4 * c + 1], scale, zero),
-                                                   qdecode(k, v[4 * c + 2], scale, zero),
-                                                   qdecode(k, v[4 * c + 3], scale, zero));
+        for (int u = 0; u < 4; u++) {
+            const int64_t c = c0 + (int64_t)u * blockDim.x;
+            if (c >= n4) break;
+            ((float4 *)x)[c] = make_float4(qdecode(k, v[u][0], scale, zero), qdecode(k, v[u][1], scale, zero),
+                                           qdecode(k, v[u][2], scale, zero), qdecode(k, v[u][3], scale, zero));
+        }
     }
-    for (int64_t i = n16 * 16 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    for (int64_t i = n4 * 4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         float q = KIND == 0 ? __half2float(((const __half *)codes)[i]) : (float)((const int8_t *)codes)[i];
         x[i] = qdecode(k, q, scale, zero);
@@ -295,31 +301,39 @@ __global__ void __launch_bounds__(256) quantize_int4_kernel(const float *__restr
     }
 }
 
+// decoding is lane-contiguous like the whole-tensor kinds: chunk c holds
+// values 4c..4c+3 (two bytes of codes), all in group 4c / G
 template <int T>
 __global__ void __launch_bounds__(256) dequantize_int4_kernel(const uint8_t *__restrict__ codes, int64_t n,
                                                               const float *__restrict__ scales,
                                                               const float *__restrict__ zeros, float *__restrict__ x) {
     constexpr int G = 16 * T;
     const QKind k = qkind(2);
-    const int64_t n16 = (n + 15) / 16;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n16; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t base = 16 * t, gi = base / G;
-        const float scale = scales[gi], zero = zeros[gi];
-        if (base + 16 <= n) {
-            uint2 c = *(const uint2 *)(codes + base / 2);
-            uint32_t w[2] = {c.x, c.y};
-            float v[16];
+    const int64_t n4 = n / 4, step = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x; c0 < n4; c0 += step) {
+        float v[4][4];
 #pragma unroll
-            for (int i = 0; i < 16; i++) v[i] = qdecode(k, (float)((w[i / 8] >> (4 * (i % 8))) & 15u), scale, zero);
+        for (int u = 0; u < 4; u++) {
+            const int64_t c = c0 + (int64_t)u * blockDim.x;
+            if (c >= n4) break;
+            const uint32_t b = ((const uint16_t *)codes)[c];
+            const int64_t gi = (4 * c) / G;
+            const float scale = scales[gi], zero = zeros[gi];
 #pragma unroll
-            for (int c4 = 0; c4 < 4; c4++)
-                ((float4 *)(x + base))[c4] = make_float4(v[4 * c4], v[4 * c4 + 1], v[4 * c4 + 2], v[4 * c4 + 3]);
-        } else {
-            for (int i = 0; i < 16 && base + i < n; i++) {
-                uint32_t b = codes[(base + i) / 2];
-                x[base + i] = qdecode(k, (float)((b >> (4 * ((base + i) & 1))) & 15u), scale, zero);
-            }
+            for (int i = 0; i < 4; i++) v[u][i] = qdecode(k, (float)((b >> (4 * i)) & 15u), scale, zero);
         }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t c = c0 + (int64_t)u * blockDim.x;
+            if (c >= n4) break;
+            ((float4 *)x)[c] = make_float4(v[u][0], v[u][1], v[u][2], v[u][3]);
+        }
+    }
+    for (int64_t i = n4 * 4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = codes[i / 2];
+        const int64_t gi = i / G;
+        x[i] = qdecode(k, (float)((b >> (4 * (i & 1))) & 15u), scales[gi], zeros[gi]);
     }
 }
 
