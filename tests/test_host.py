@@ -170,3 +170,22 @@ def test_slice_path_meets_a_lower_cap():
     assert set(sl) <= set(more.tolist()) and len(more) > len(sl)
     assert T.tnc_plan_analyze(net, ssa, more, open_q, "c64")["max_rank"] <= before - 2
     T.tnc_network_destroy(net)
+
+
+def test_stored_53_qubit_path_layouts_keep_permutes_low():
+    """The planner reads two-run operand layouts in place and orders each result
+    for its consumer: on the stored 53-qubit path at most 1e11 permute bytes per
+    slice remain (a plain [batch][free][contracted] layout for every operand
+    would move about 3.75e11)."""
+    import json
+    path = json.load(open(os.path.join(ROOT, "paper_2407_00769_amd", "paths", "config3.json")))
+    c = workloads.config_circuit(3)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    info = T.tnc_plan_analyze(net, np.array(path["ssa"], np.int32), np.array(path["sliced"], np.int32),
+                              path["open_qubits"], "f16_4m")
+    assert info["max_rank"] == 33
+    assert info["permute_bytes_per_slice"] <= 1.0e11, info["permute_bytes_per_slice"]
+    assert 2.3e14 < info["flops_per_slice"] < 2.6e14
+    T.tnc_network_destroy(net)
