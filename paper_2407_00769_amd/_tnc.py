@@ -26,6 +26,15 @@ MLP_HIDDEN = 128
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
 
+# libtnc.so needs the HIP runtime by its soname, libamdhip64.so.7.  torch ships
+# its own copy of that runtime (same soname, different file) and loads it by
+# path.  Loading torch first lets the dynamic loader satisfy libtnc.so's need
+# with torch's copy, so the process holds one HIP runtime and one ROCr, and
+# device memory and streams that torch hands over are valid in the library.
+# Loading libtnc.so first would map /opt/rocm's copies beside torch's, and the
+# library's runtime would then see no device.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
