@@ -88,6 +88,8 @@ typedef struct {
     double peak_bytes;             /* arena bytes needed at slices_in_flight               */
     double peak_elems_per_slice;   /* largest tensor of one slice, in complex entries      */
     double tune_seconds;           /* host time spent timing kernel variants at plan time  */
+    int32_t n_host_steps;          /* steps of the given path contracted on the host in     */
+                                   /* FP64 before the device path (not in n_steps)          */
 } tnc_plan_stats;
 
 /* Results of one tnc_execute. */
@@ -120,9 +122,14 @@ int tnc_destroy(tnc_ctx *ctx);
  *   (first label slowest), each label id in [0, 2^30);
  * data_c128: the concatenation of every tensor's 2^rank complex entries as
  *   interleaved (re, im) doubles; copied.
- * output_labels[n_qubits]: the open leg of qubit q (its last wire).
- * A label must occur in exactly two tensors, or in one tensor when it is an
- * output label; no label may repeat within a tensor.  Otherwise TNC_EINVAL. */
+ * output_labels[n_qubits]: the open leg of qubit q (its last wire); each
+ *   occurs in at least one tensor, and no two qubits share one.
+ * No label may repeat within a tensor (TNC_EINVAL).  A label held by one
+ * tensor only that is not an output label is summed over here, in FP64 (the
+ * reduction of Sec. 3.3, Eq. contraction, applied to a single operand).  A
+ * label held by three or more tensors (a hyperedge) is accepted by the plan
+ * calls, which keep it as a batch label until its last holder is contracted;
+ * tnc_search and tnc_slice_path return TNC_EUNSUPPORTED for such networks. */
 int tnc_network_create(int32_t n_tensors, const int32_t *ranks, const int32_t *labels,
                        const double *data_c128, int32_t n_qubits, const int32_t *output_labels,
                        tnc_network **out);
@@ -133,8 +140,8 @@ int tnc_network_destroy(tnc_network *net);
 /* Find a contraction path and sliced labels for `net` with the qubits in
  * open_qubits[n_open] left open and every other qubit closed.
  * log2_cap: per-slice limit on the largest tensor, log2 of complex entries.
- * cost_model: 0 = FLOP/byte cost, 1 = the learned step-time model loaded with
- *   tnc_costmodel_load (falls back to 0 when none is loaded).
+ * cost_model: 0 = FLOP/byte cost, 1 = the learned step-time model made
+ *   active with tnc_costmodel_use (falls back to 0 when none is active).
  * restarts: randomized greedy trials (>= 1); seed makes the result
  *   deterministic.
  * ssa_out: host, capacity 2*(n_tensors-1) ints; receives the path as

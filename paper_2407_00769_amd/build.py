@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtnc.so")
-SOURCES = ["kernels.hip", "gemm.hip", "mlp.hip", "codec.hip", "planner.cpp", "engine.cpp", "contract.cpp",
+SOURCES = ["kernels.hip", "gemm.hip", "mlp.hip", "codec.hip", "planner.cpp", "simplify.cpp", "engine.cpp", "contract.cpp",
            "search.cpp", "codec.cpp", "postselect.hip", "postselect.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

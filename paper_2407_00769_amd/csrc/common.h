@@ -56,6 +56,7 @@ struct Network {
     int n_qubits = 0;
     std::vector<int> output_labels;            // per qubit
     int n_labels = 0;                          // 1 + max label id
+    bool hyperedges = false;                   // some label is held by three or more tensors
 };
 
 // ------------------------------------------------------------------ kernel launch descriptors

@@ -130,11 +130,31 @@ extern "C" int tnc_network_create(int32_t n_tensors, const int32_t *ranks, const
             is_out[l] = 1;
             net.output_labels.push_back(l);
         }
-        for (int l = 0; l < net.n_labels; l++) {
-            if (cnt[l] == 0) continue;
-            if (is_out[l]) REQUIRE(cnt[l] == 1, "output label " + std::to_string(l) + " occurs in more than one tensor");
-            else REQUIRE(cnt[l] == 2, "label " + std::to_string(l) + " must occur in exactly two tensors");
+        // A label held by one tensor only, and not an output label, is summed
+        // over here (paper Eq. contraction: a label that no other operand
+        // holds and the result does not keep is reduced), in FP64.  A label
+        // held by three or more tensors (a hyperedge) stays; the device path
+        // keeps it as a batch label until its last holder is contracted.
+        for (int i = 0; i < n_tensors; i++) {
+            std::vector<int> &ls = net.labels[i];
+            for (int j = (int)ls.size() - 1; j >= 0; j--) {
+                const int l = ls[j];
+                if (cnt[l] != 1 || is_out[l]) continue;
+                const int r = (int)ls.size();
+                const int64_t n_out = (int64_t)1 << (r - 1), lo = (int64_t)1 << (r - 1 - j);
+                std::vector<double> d(2 * n_out, 0.0);
+                for (int64_t o = 0; o < n_out; o++) {
+                    const int64_t base = (o / lo) * 2 * lo + (o % lo);   // label bit 0
+                    d[2 * o] = net.data[i][2 * base] + net.data[i][2 * (base + lo)];
+                    d[2 * o + 1] = net.data[i][2 * base + 1] + net.data[i][2 * (base + lo) + 1];
+                }
+                net.data[i].swap(d);
+                ls.erase(ls.begin() + j);
+                cnt[l] = 0;
+            }
         }
+        for (int l = 0; l < net.n_labels; l++)
+            if (cnt[l] > 2) net.hyperedges = true;
     } catch (...) {
         delete nw;
         throw;
@@ -486,8 +506,13 @@ extern "C" int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_s
     auto *p = new tnc_plan;
     p->ctx = ctx;
     try {
-        p->an = analyze(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits, prec);
-        build_plan(p, net->net, max_slices_in_flight);
+        Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits,
+                                    host_rank_cap());
+        p->plan_step_of = sp.plan_step_of;
+        p->host_steps = sp.host_steps;
+        p->an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), n_sliced, sliced_labels, n_open, open_qubits,
+                        prec);
+        build_plan(p, sp.net, max_slices_in_flight);
         p->tune_seconds = autotune_plan(p);
     } catch (...) {
         free_plan_device(p);
@@ -511,6 +536,7 @@ extern "C" int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats) {
     API_BEGIN
     REQUIRE(plan && stats, "NULL argument");
     fill_stats(plan->an, *stats);
+    stats->n_host_steps = plan->host_steps;
     stats->slices_in_flight = plan->S;
     stats->peak_bytes = (double)plan->peak;
     stats->tune_seconds = plan->tune_seconds;
@@ -523,8 +549,12 @@ extern "C" int tnc_plan_analyze(const tnc_network *net, int32_t n_steps, const i
     API_BEGIN
     REQUIRE(net && stats, "NULL argument");
     REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
-    Analysis an = analyze(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits, prec);
+    Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits,
+                                host_rank_cap());
+    Analysis an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), n_sliced, sliced_labels, n_open, open_qubits,
+                          prec);
     fill_stats(an, *stats);
+    stats->n_host_steps = sp.host_steps;
     stats->slices_in_flight = 0;
     stats->peak_bytes = (double)plan_memory(an, 1, false);
     API_END
@@ -679,7 +709,12 @@ void enqueue_block(tnc_plan *p, int64_t nsl, int64_t nbits, hipStream_t st, bool
 extern "C" int tnc_plan_set_codec(tnc_plan *plan, int32_t step, int32_t kind, int32_t group) {
     API_BEGIN
     REQUIRE(plan, "plan is NULL");
-    REQUIRE(step >= -1 && step < (int)plan->an.steps.size(), "step out of range");
+    REQUIRE(step >= -1 && step < (int)plan->plan_step_of.size(), "step out of range");
+    if (step >= 0) {
+        if (plan->plan_step_of[step] < 0)
+            TNC_THROW(TNC_EUNSUPPORTED, "step " + std::to_string(step) + " is pre-contracted on the host");
+        step = plan->plan_step_of[step];
+    }
     if (step >= 0 && plan->an.dt != Dtype::C64)
         TNC_THROW(TNC_EUNSUPPORTED, "the codec round trip applies to complex64 plans (float32 values)");
     int64_t cb = 0, ng = 0;
@@ -768,7 +803,11 @@ extern "C" int tnc_plan_analyze_steps(const tnc_network *net, int32_t n_steps, c
                                       int32_t *kernel, int32_t *dep, int32_t *perm_ab, double *flops, double *bytes) {
     API_BEGIN
     REQUIRE(net, "net is NULL");
-    Analysis an = analyze(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits, prec);
+    REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
+    Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits,
+                                host_rank_cap());
+    Analysis an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), n_sliced, sliced_labels, n_open, open_qubits,
+                          prec);
     describe_steps(an, n_steps, log2_mnkb, kernel, dep, perm_ab, flops, bytes);
     API_END
 }

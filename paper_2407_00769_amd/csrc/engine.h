@@ -36,6 +36,8 @@ struct tnc_ctx {
 struct tnc_plan {
     tnc_ctx *ctx = nullptr;
     tnc::Analysis an;
+    std::vector<int> plan_step_of;     // per step of the caller's path: device step, or -1 (run on the host)
+    int host_steps = 0;                // steps pre-contracted on the host in FP64
     int S = 1;                         // slices in flight
     int64_t peak = 0;
     int nT = 0;                        // input tensors

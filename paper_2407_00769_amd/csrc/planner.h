@@ -73,4 +73,22 @@ PermuteDesc make_permute(const std::vector<int> &from, const std::vector<int> &t
 
 void fill_stats(const Analysis &an, tnc_plan_stats &st);
 
+// Host FP64 pre-contraction (simplify.cpp): the steps of a path whose operands
+// are input tensors or results of such steps, one of them of rank <= 2, and
+// whose result is no larger than the larger operand and has at most
+// `max_rank` labels (fixed labels included), are contracted on the host in
+// complex128; `net` and `ssa` are the device's leaves and path.
+constexpr int kDefaultHostRank = 10;
+constexpr int kMaxHostRank = 14;
+struct Simplified {
+    Network net;
+    std::vector<int32_t> ssa;
+    std::vector<int> plan_step_of;   // per step of the given path: device step, or -1 (host)
+    int host_steps = 0;
+};
+// rank cap of host steps: TNC_HOST_RANK if set (0 switches the pass off), else kDefaultHostRank
+int host_rank_cap();
+Simplified presimplify(const Network &net, int n_steps, const int32_t *ssa, int n_sliced, const int32_t *sliced,
+                       int n_open, const int32_t *open_q, int max_rank);
+
 }  // namespace tnc

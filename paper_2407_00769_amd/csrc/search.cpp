@@ -416,6 +416,7 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
         if (!net_h || !ssa_out || !n_sliced || (max_sliced > 0 && !sliced_out)) TNC_THROW(TNC_EINVAL, "NULL argument");
         const Network &net = net_h->net;
         if (restarts < 1) TNC_THROW(TNC_EINVAL, "restarts < 1");
+        if (net.hyperedges) TNC_THROW(TNC_EUNSUPPORTED, "the search takes networks whose labels join two tensors");
         if (net.n_tensors < 2) TNC_THROW(TNC_EUNSUPPORTED, "a network of one tensor has nothing to contract");
         const int L = net.n_labels;
         std::vector<char> gone(L, 0), sliceable(L, 1), is_open(net.n_qubits, 0);
@@ -529,6 +530,7 @@ extern "C" int tnc_slice_path(const tnc_network *net_h, int32_t n_steps, const i
         if (!net_h || !ssa_pairs || !sliced_out || !n_out || (n_in > 0 && !sliced_in)) TNC_THROW(TNC_EINVAL, "NULL argument");
         const Network &net = net_h->net;
         if (n_steps != net.n_tensors - 1) TNC_THROW(TNC_EINVAL, "path must have n_tensors - 1 steps");
+        if (net.hyperedges) TNC_THROW(TNC_EUNSUPPORTED, "the slicer takes networks whose labels join two tensors");
         const int L = net.n_labels;
         std::vector<char> gone(L, 0), sliceable(L, 1), is_open(net.n_qubits, 0);
         for (int i = 0; i < n_open; i++) {

@@ -38,19 +38,58 @@ def _net(cfg=0, cycles=None):
 
 
 def test_network_validation_errors():
-    # a label in three tensors
-    with pytest.raises(T.TncError) as e:
-        T.tnc_network_create([1, 1, 1], [0, 0, 0], None, 0, [])
-    assert e.value.code == -1
     # repeated label inside one tensor
-    with pytest.raises(T.TncError):
+    with pytest.raises(T.TncError) as e:
         T.tnc_network_create([2], [3, 3], None, 0, [])
-    # dangling label that is not an output
+    assert e.value.code == -1
+    # an output label that no tensor holds, two qubits on one output label
     with pytest.raises(T.TncError):
-        T.tnc_network_create([2, 1], [0, 1, 0], None, 0, [])
+        T.tnc_network_create([2, 2], [0, 1, 0, 2], None, 2, [1, 5])
+    with pytest.raises(T.TncError):
+        T.tnc_network_create([2, 2], [0, 1, 0, 2], None, 2, [1, 1])
     # fine: two tensors sharing a label, an output on each
     h = T.tnc_network_create([2, 2], [0, 1, 0, 2], None, 2, [1, 2])
     T.tnc_network_destroy(h)
+
+
+def test_hyperedges_are_planned_and_lonely_labels_summed():
+    """A label in three tensors is accepted by the plan calls (kept as a batch
+    label until its last holder) and refused by the search; a label held by
+    one tensor that is not an output is summed at creation."""
+    # tensors: X[h, a], Y[h, b], W[h, c]; outputs a, b, c; hyperedge h
+    data = np.arange(1, 13, dtype=np.float64)
+    h = T.tnc_network_create([2, 2, 2], [0, 1, 0, 2, 0, 3], data, 3, [1, 2, 3])
+    with pytest.raises(T.TncError) as e:
+        T.tnc_search(h, 3, [0, 1, 2], 30, restarts=1, seed=0)
+    assert e.value.code == -5
+    st = T.tnc_plan_analyze(h, np.array([0, 1, 3, 2], np.int32), [], [0, 1, 2], "c64")
+    assert st["n_steps"] + st["n_host_steps"] == 2 and st["out_rank"] == 3
+    T.tnc_network_destroy(h)
+    # X[a, d] with d held by X only: X becomes the rank-1 tensor sum_d X[a, d]
+    h = T.tnc_network_create([2, 1], [1, 9, 1], np.arange(1, 13, dtype=np.float64), 0, [])
+    st = T.tnc_plan_analyze(h, np.array([0, 1], np.int32), [], [], "c64")
+    assert st["out_rank"] == 0 and st["max_rank"] == 1
+    T.tnc_network_destroy(h)
+
+
+def test_host_pre_contraction_keeps_the_device_path_small():
+    """Steps that absorb rank-1/2 tensors run on the host; the device path
+    keeps the rest of the given tree, and every step is accounted for."""
+    import os as _os
+    c, st, net, n = _net(0)
+    ssa, sl, _ = T.tnc_search(net, n, list(range(6, 12)), 8, restarts=2, seed=0)
+    full = T.tnc_plan_analyze(net, ssa, sl, list(range(6, 12)), "f16_4m")
+    assert full["n_host_steps"] > 0
+    assert full["n_steps"] + full["n_host_steps"] == n - 1
+    _os.environ["TNC_HOST_RANK"] = "0"
+    try:
+        plain = T.tnc_plan_analyze(net, ssa, sl, list(range(6, 12)), "f16_4m")
+    finally:
+        del _os.environ["TNC_HOST_RANK"]
+    assert plain["n_host_steps"] == 0 and plain["n_steps"] == n - 1
+    # the large steps are the same: the flops differ by the tiny host steps only
+    assert abs(full["flops_per_slice"] - plain["flops_per_slice"]) <= 0.01 * plain["flops_per_slice"]
+    assert full["out_rank"] == plain["out_rank"] == 6
 
 
 def test_search_returns_a_valid_tree_and_meets_the_cap():
@@ -113,7 +152,8 @@ def _einsum_flops(tensors, ssa, open_labels):
     return total
 
 
-def test_planner_flops_match_label_count():
+def test_planner_flops_match_label_count(monkeypatch):
+    monkeypatch.setenv("TNC_HOST_RANK", "0")   # every step of the path on the device
     c, st, net, n = _net(0)
     open_q = list(range(12))
     ssa, sl, _ = T.tnc_search(net, n, open_q, 30, restarts=2, seed=3)
@@ -127,7 +167,8 @@ def test_smoke_case_is_sliced_under_its_cap():
     import __graft_entry__ as ge
     from paper_2407_00769_amd import _tnc as T
     c, net, ssa, sl, open_q, bits = ge.smoke_case()
-    assert len(sl) > 0 and len(ssa) == 2 * (T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")["n_steps"])
+    info = T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")
+    assert len(sl) > 0 and len(ssa) == 2 * (info["n_steps"] + info["n_host_steps"])
     assert T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")["max_rank"] <= 8
     T.tnc_network_destroy(net)
 
