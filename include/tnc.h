@@ -208,6 +208,22 @@ int tnc_plan_analyze_steps(const tnc_network *net, int32_t n_steps, const int32_
 int tnc_execute(tnc_plan *plan, int64_t n_bitstrings, const uint64_t *bitstrings, int64_t slice_begin,
                 int64_t slice_end, double *out_c128, tnc_report *rep);
 
+/* Growth estimates of the scale epilogue (16-bit forms; not in the paper,
+ * which computes in complex-half without per-tensor scaling).  Every 16-bit
+ * step stores C * 2^-t with t = floor(log2 maxA) + floor(log2 maxB) + g - 13,
+ * maxA / maxB its operands' largest stored components, so that the result's
+ * largest stored component lands near 2^13; g is the step's growth estimate,
+ * log2 of max|C| / (max|A| max|B|).  A stored maximum above 32752 (FP16: half
+ * the range, so that a 3M consumer's re + im stays finite) or a non-finite
+ * value flags the step; tnc_execute then raises the flagged steps' g by 4 and
+ * runs the block again, at most 3 times (TNC_EOVERFLOW after that).  After
+ * every successful call each g becomes ceil of the largest growth realized
+ * by the slices of the last group, so estimates narrow as well as widen.
+ * growth: host, one int per device step of the plan (tnc_plan_info n_steps),
+ * values in [-64, 64].  TNC_EINVAL for complex64 plans (set) or a wrong count. */
+int tnc_plan_get_growth(const tnc_plan *plan, int32_t n_steps, int32_t *growth);
+int tnc_plan_set_growth(tnc_plan *plan, int32_t n_steps, const int32_t *growth);
+
 /* Per-step device times of the last tnc_execute run with step timing on
  * (tnc_plan_set_timing; timed runs launch step by step, not as one graph).
  * Host arrays of capacity n_steps (each may be NULL): gemm_ms[t] and

@@ -93,6 +93,8 @@ _SIGS = {
     "tnc_plan_set_codec": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "tnc_topk": (ctypes.c_int, [vp, ctypes.c_int64, vp, ctypes.c_int32, vp, vp, c_double_p]),
     "tnc_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int32]),
+    "tnc_plan_get_growth": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p]),
+    "tnc_plan_set_growth": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p]),
     "tnc_plan_step_times": (ctypes.c_int, [vp, ctypes.c_int32, c_double_p, c_double_p, c_int32_p]),
     "tnc_plan_steps": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, c_int32_p, c_int32_p, c_int32_p, c_double_p,
                                       c_double_p]),
@@ -261,6 +263,18 @@ def tnc_execute(plan, bitstrings, slice_begin, slice_end, out=None):
 
 def tnc_plan_set_timing(plan, on: bool):
     _check(lib.tnc_plan_set_timing(plan, int(bool(on))))
+
+
+def tnc_plan_get_growth(plan) -> np.ndarray:
+    n = tnc_plan_info(plan)["n_steps"]
+    g = np.zeros(n, dtype=np.int32)
+    _check(lib.tnc_plan_get_growth(plan, n, g.ctypes.data_as(c_int32_p)))
+    return g
+
+
+def tnc_plan_set_growth(plan, growth):
+    g = np.ascontiguousarray(growth, dtype=np.int32)
+    _check(lib.tnc_plan_set_growth(plan, len(g), g.ctypes.data_as(c_int32_p)))
 
 
 def tnc_plan_step_times(plan, n_steps):

@@ -6,9 +6,9 @@
 
 using namespace tnc;
 
-namespace {
+namespace tnc {
 
-int resolve_group(int32_t kind, int32_t group) {
+int codec_group(int32_t kind, int32_t group) {
     if (kind < 0 || kind > 2) TNC_THROW(TNC_EINVAL, "unknown codec kind");
     if (kind != 2) {
         if (group != 0) TNC_THROW(TNC_EINVAL, "half and int8 use one group (the whole tensor): pass group 0");
@@ -20,6 +20,10 @@ int resolve_group(int32_t kind, int32_t group) {
     TNC_THROW(TNC_EINVAL, "int4 group size must be a power of two from 16 to 1024");
 }
 
+}  // namespace tnc
+
+namespace {
+
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 }  // namespace
@@ -27,7 +31,7 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 extern "C" int tnc_quant_sizes(int32_t kind, int64_t n, int32_t group, int64_t *code_bytes, int64_t *n_groups) {
     try {
         if (n < 0) TNC_THROW(TNC_EINVAL, "negative length");
-        const int g = resolve_group(kind, group);
+        const int g = codec_group(kind, group);
         const int64_t cb = kind == 0 ? 2 * n : (kind == 1 ? n : (n + 1) / 2);
         const int64_t ng = kind == 2 ? (n + g - 1) / g : (n > 0 ? 1 : 0);
         if (code_bytes) *code_bytes = cb;
@@ -44,7 +48,7 @@ extern "C" int tnc_quantize(tnc_ctx *ctx, int32_t kind, int64_t n, const float *
     try {
         if (!ctx) TNC_THROW(TNC_EINVAL, "NULL context");
         if (n < 0) TNC_THROW(TNC_EINVAL, "negative length");
-        const int g = resolve_group(kind, group);
+        const int g = codec_group(kind, group);
         if (n == 0) {
             if (ms_out) *ms_out = 0.0;
             return TNC_OK;
@@ -77,7 +81,7 @@ extern "C" int tnc_dequantize(tnc_ctx *ctx, int32_t kind, int64_t n, const void 
     try {
         if (!ctx) TNC_THROW(TNC_EINVAL, "NULL context");
         if (n < 0) TNC_THROW(TNC_EINVAL, "negative length");
-        const int g = resolve_group(kind, group);
+        const int g = codec_group(kind, group);
         if (n == 0) {
             if (ms_out) *ms_out = 0.0;
             return TNC_OK;

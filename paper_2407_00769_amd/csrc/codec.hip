@@ -348,7 +348,7 @@ void launch_quantize(int kind, int64_t n, int group, const float *x, void *codes
                      float2 *part, hipStream_t st) {
     if (n <= 0) return;
     if (kind == 0 || kind == 1) {
-        const int np = grid_cap(n, 256 * 64, 512);   // partials: 512 float2 = the 4 KB part buffer
+        const int np = grid_cap(n, 256 * 64, kQuantPartials);   // partials: 512 float2 = a 4 KB buffer
         hipLaunchKernelGGL(minmax_partial_kernel, dim3(np), dim3(256), 0, st, x, n, part);
         hipLaunchKernelGGL(scale_zero_kernel, dim3(1), dim3(64), 0, st, (const float2 *)part, np, kind, scales, zeros);
         const int g = grid_cap(n / 16 + 1, 256, 8192);

@@ -102,6 +102,7 @@ struct GemmShape {
     // pairs) and a second kernel sums the parts in order
     int64_t split = 1;
     float2 *part = nullptr;
+    int64_t part_cap = 0;       // bytes available at `part` (checked on the host before a split launch)
     // the split factor is chosen for this many slices per launch, the count
     // the partial buffer was sized for (0: the launch's own count); a launch
     // over fewer slices keeps that factor, so it never needs more buffer
@@ -119,10 +120,23 @@ struct ScaleRefs {
     int *shift;                     // per slice (written), may be null
     const int *growth;              // device int: expected log2 growth of this step
     uint32_t *flag;                 // set nonzero on range overflow
+    // a stored maximum above this flags the step (set by launch_gemm from the
+    // storage type): FP16 results must stay below half the FP16 range so that
+    // a consumer's 3M sum plane (re + im) stays finite
+    float flag_above = 3.0e38f;
 };
 
 // Target exponent of the largest stored 16-bit component (see device_util.h).
 constexpr int kTargetLog2Host = 13;
+// Largest FP16 stored component a step may leave: half of 65504, so that the
+// sum re + im a 3M consumer forms is at most the largest finite FP16 value.
+constexpr float kF16FlagAbove = 32752.0f;
+
+// Exchange codec: the group size a kind uses (group 0 = the kind's default);
+// throws TNC_EINVAL for an unknown kind or group size.
+int codec_group(int32_t kind, int32_t group);
+// Partials of the codec's whole-tensor min/max pass (one float2 per block).
+constexpr int kQuantPartials = 512;
 
 // Kernel variant ids (autotuned per step).
 enum KernelId : int {

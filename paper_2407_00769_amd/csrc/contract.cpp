@@ -205,7 +205,10 @@ extern "C" int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int
         }
         // split-K partial sums go to the workspace after the permute scratch
         int64_t pb = splitk_bytes(kid, dt, al, g, 1);
-        if (pb > 0 && (size_t)(off + pb) <= ctx->ws_bytes) g.part = (float2 *)(ctx->ws + off);
+        if (pb > 0 && (size_t)(off + pb) <= ctx->ws_bytes) {
+            g.part = (float2 *)(ctx->ws + off);
+            g.part_cap = pb;
+        }
         launch_gemm(kid, dt, al, pr, pq, pc, g, 1, dt != Dtype::C64 ? &sc : nullptr, st);
         HIP_CHECK(hipEventRecord(ev[3], st));
         if (perm_c) launch_permute(dt, pc, C, make_permute(gemm_c, lc), nc, 1, 0, nullptr, 0, st);

@@ -308,6 +308,7 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
             part_bytes = std::max(part_bytes, splitk_bytes(k, dt, an.al, g, rec.dep ? S : 1));
     }
     if (part_bytes > 0) p->d_part = (float2 *)dev_alloc<uint8_t>(part_bytes);
+    p->part_bytes = part_bytes;
     p->step_ms.assign(ns, 0.0);
     p->perm_ms.assign(ns, 0.0);
     p->step_launches.assign(ns, 0);
@@ -418,8 +419,11 @@ double autotune_plan(tnc_plan *p) {
         g.sB = B.dep ? nbb : 0;
         g.sC = nz;
         g.part = p->d_part;
+        g.part_cap = p->part_bytes;
         const int Sl = rec.dep ? p->S : 1;
         g.split_slices = Sl;
+        // the per-slice bookkeeping of the tuning launches holds S_t slices
+        if (Sl > S_t) TNC_THROW(TNC_EINVAL, "internal: tuning launch covers more slices than its scratch holds");
         std::vector<int> cands;
         // big steps: only the large matrix-core tiles are worth timing
         const bool big = rec.flops * (double)Sl > 1e13;
@@ -608,6 +612,7 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
     g.sB = B.dep ? nbb : 0;
     g.sC = nz;
     g.part = p->d_part;
+    g.part_cap = p->part_bytes;
     g.split_slices = rec.dep ? p->S : 1;   // the slice count d_part was sized for
     (void)es;
     ScaleRefs sc{};
@@ -812,6 +817,85 @@ extern "C" int tnc_plan_analyze_steps(const tnc_network *net, int32_t n_steps, c
     API_END
 }
 
+namespace {
+
+// floor(log2 x) of a positive finite float, as the device takes it (frexp)
+int floor_log2_host(float x) {
+    int e = 0;
+    std::frexp(x, &e);
+    return e - 1;
+}
+
+// Growth estimates for the next call, from the slices of the last group.  A
+// step stores C * 2^-t with t = floor(log2 mA) + floor(log2 mB) + g - target
+// (mA, mB: its operands' stored maxima), so its stored maximum mC tells the
+// realized growth
+//     gamma = log2 mC + t - floor(log2 mA) - floor(log2 mB),
+// the estimate that would have put mC at 2^target exactly.  Each step keeps
+// ceil(max gamma) over the group's slices: the estimate narrows when a step
+// grows less than planned, and widens again after a replay.
+void adapt_growth(tnc_plan *p, int S_last) {
+    const Analysis &an = p->an;
+    const int S = p->S;
+    const int64_t nslots = (int64_t)an.tensors.size() * S;
+    std::vector<uint32_t> mw(nslots);
+    std::vector<int> sh(nslots);
+    HIP_CHECK(hipMemcpy(mw.data(), p->d_maxw, sizeof(uint32_t) * nslots, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(sh.data(), p->d_shift, sizeof(int) * nslots, hipMemcpyDeviceToHost));
+    auto val = [&](int t, int q) {
+        float f;
+        std::memcpy(&f, &mw[(int64_t)t * S + q], 4);
+        return f;
+    };
+    bool changed = false;
+    for (size_t s = 0; s < an.steps.size(); s++) {
+        const StepRec &rec = an.steps[s];
+        const bool da = an.tensors[rec.a].dep, db = an.tensors[rec.b].dep;
+        const int Sl = rec.dep ? S_last : 1;
+        double gmax = -1e300;
+        for (int q = 0; q < Sl; q++) {
+            const float ma = val(rec.a, da ? q : 0), mb = val(rec.b, db ? q : 0), mc = val(rec.z, q);
+            if (!(ma > 0.f && mb > 0.f && mc > 0.f) || !(ma <= 3.0e38f && mb <= 3.0e38f && mc <= 3.0e38f)) continue;
+            const int t = sh[(int64_t)rec.z * S + q];
+            const double gam = std::log2((double)mc) + t - floor_log2_host(ma) - floor_log2_host(mb);
+            gmax = std::max(gmax, gam);
+        }
+        if (gmax < -1e299) continue;
+        const int g = (int)std::max(-64.0, std::min(64.0, std::ceil(gmax - 1e-9)));
+        if (g != p->h_growth[s]) {
+            p->h_growth[s] = g;
+            changed = true;
+        }
+    }
+    if (changed)
+        HIP_CHECK(hipMemcpyAsync(p->d_growth, p->h_growth.data(), sizeof(int) * p->h_growth.size(),
+                                 hipMemcpyHostToDevice, p->ctx->stream));
+}
+
+}  // namespace
+
+extern "C" int tnc_plan_get_growth(const tnc_plan *plan, int32_t n_steps, int32_t *growth) {
+    API_BEGIN
+    REQUIRE(plan && growth, "NULL argument");
+    REQUIRE(n_steps >= (int)plan->h_growth.size(), "array too small");
+    for (size_t s = 0; s < plan->h_growth.size(); s++) growth[s] = plan->h_growth[s];
+    API_END
+}
+
+extern "C" int tnc_plan_set_growth(tnc_plan *plan, int32_t n_steps, const int32_t *growth) {
+    API_BEGIN
+    REQUIRE(plan && growth, "NULL argument");
+    REQUIRE(n_steps == (int)plan->h_growth.size(), "n_steps must equal the plan's step count");
+    for (int s = 0; s < n_steps; s++) REQUIRE(growth[s] >= -64 && growth[s] <= 64, "growth out of [-64, 64]");
+    REQUIRE(plan->an.dt != Dtype::C64, "complex64 plans keep no scale exponents");
+    HIP_CHECK(hipSetDevice(plan->ctx->device));
+    for (int s = 0; s < n_steps; s++) plan->h_growth[s] = growth[s];
+    HIP_CHECK(hipMemcpyAsync(plan->d_growth, plan->h_growth.data(), sizeof(int) * n_steps, hipMemcpyHostToDevice,
+                             plan->ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(plan->ctx->stream));
+    API_END
+}
+
 extern "C" int tnc_execute(tnc_plan *p, int64_t n_bitstrings, const uint64_t *bitstrings, int64_t slice_begin,
                            int64_t slice_end, double *out_c128, tnc_report *rep) {
     API_BEGIN
@@ -875,12 +959,14 @@ extern "C" int tnc_execute(tnc_plan *p, int64_t n_bitstrings, const uint64_t *bi
     int64_t params[4] = {slice_begin, 0, 0, 0};
     HIP_CHECK(hipMemcpyAsync(p->d_params, params, sizeof(params), hipMemcpyHostToDevice, st));
 
+    const int ns = (int)an.steps.size();
+    // overflow flags start clear (a call that ended in TNC_EOVERFLOW leaves them set)
+    if (an.dt != Dtype::C64) launch_fill_u32(p->d_flags, 0u, ns, st);
     hipEvent_t ev0, ev1;
     HIP_CHECK(hipEventCreate(&ev0));
     HIP_CHECK(hipEventCreate(&ev1));
     int replays = 0, launches = 0;
     float ms = 0.f;
-    const int ns = (int)an.steps.size();
     for (;;) {
         if (p->timing) {
             std::fill(p->step_ms.begin(), p->step_ms.end(), 0.0);
@@ -929,7 +1015,10 @@ extern "C" int tnc_execute(tnc_plan *p, int64_t n_bitstrings, const uint64_t *bi
                 any = true;
                 p->h_growth[s] += 4;
             }
-        if (!any) break;
+        if (!any) {
+            adapt_growth(p, nsl > 0 ? (int)(nsl - ((nsl - 1) / p->S) * p->S) : 0);
+            break;
+        }
         if (replays >= 3) {
             hipEventDestroy(ev0);
             hipEventDestroy(ev1);

@@ -62,6 +62,7 @@ struct tnc_plan {
     double *d_acc = nullptr;
     int *d_qob = nullptr;
     float2 *d_part = nullptr;            // split-K partial sums (largest need over the steps)
+    int64_t part_bytes = 0;              // size of d_part
     std::vector<int> h_growth;
     std::vector<int64_t> closed_state;  // closed_off per leaf last uploaded
     // graph cache: (slices, bitstrings, bits pointer) -> executable graph

@@ -58,7 +58,7 @@ __device__ __forceinline__ void finish_max(const ScaleRefs &sc, int s, float mx)
     mx = block_max(mx);
     if (threadIdx.x == 0) {
         atomicMax(&sc.maxC[s], __float_as_uint(mx));
-        if (!(mx <= 3.0e38f) && sc.flag) atomicOr(sc.flag, 1u);   // rounded to inf, or NaN
+        if (!(mx <= sc.flag_above) && sc.flag) atomicOr(sc.flag, 1u);   // too large, inf, or NaN
     }
 }
 
@@ -1635,13 +1635,20 @@ void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void 
                  const ScaleRefs *sc, hipStream_t st) {
     if (S <= 0) return;
     if (!gemm_supported(kid, dt, al, g_in)) TNC_THROW(TNC_EINVAL, std::string("kernel ") + kernel_name(kid) + " cannot run this shape");
-    ScaleRefs none{};
-    const ScaleRefs &s = sc ? *sc : none;
+    ScaleRefs s = sc ? *sc : ScaleRefs{};
     if (dt != Dtype::C64 && !sc) TNC_THROW(TNC_EINVAL, "16-bit forms need scale bookkeeping");
+    s.flag_above = dt == Dtype::F16 ? kF16FlagAbove : 3.0e38f;
     GemmShape g = g_in;
     const int64_t split_s = g.split_slices > 0 ? g.split_slices : S;
     if (S > split_s) TNC_THROW(TNC_EINVAL, "launch covers more slices than its split-K buffer was sized for");
     g.split = g.part ? splitk_factor(kid, dt, al, g, (int)split_s) : 1;
+    if (g.split > 1) {
+        // the parts of this launch: split x S slices x batch x M x N (re, im) pairs
+        const int64_t need = g.split * (int64_t)S * g.nb * g.M * g.N * (int64_t)sizeof(float2);
+        if (need > g.part_cap)
+            TNC_THROW(TNC_EINVAL, "internal: split-K partial sums need " + std::to_string(need) + " bytes, buffer has " +
+                                      std::to_string(g.part_cap));
+    }
     if (g.split > 1) {
         if (dt == Dtype::C64)
             launch_c64(kid, A, B, C, g, S, st);

@@ -85,4 +85,16 @@ def test_twin_all_slices_match_oracle(T, ctx, twin, prec, fmin, rlmax):
     if prec == "c64":
         o0, _ = T.tnc_execute(plan, twin["bits"], 0, 1)
         assert metrics.rel_l2(o0, twin["ref_0"]) <= 1e-4
+        assert metrics.rel_max(out, twin["ref_all"]) <= 1e-4
+    else:
+        # per amplitude, within the rounding model's errors on this path
+        from rounding_model import check_against_model, fmt_of, model_amplitudes
+        key = "model_" + fmt_of(prec)
+        if key not in twin:
+            c = workloads.config_circuit(3, cycles=8)
+            st = workloads.tn_structure(c)
+            twin[key] = model_amplitudes(c, st, twin["ssa"], twin["sl"], OPEN, twin["bits"], prec)
+        ok, stats = check_against_model(out, twin["ref_all"], twin[key])
+        print(prec, stats)
+        assert ok, stats
     T.tnc_plan_destroy(plan)
