@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtnc.so")
+# TNC_LIB names another build of the library (the host-code sanitizer build
+# that the CPU tests load); the default is the in-tree libtnc.so
+LIB_PATH = os.environ.get("TNC_LIB") or os.path.join(HERE, "libtnc.so")
 
 TNC_C64, TNC_F16_4M, TNC_F16_3M, TNC_BF16_4M, TNC_BF16_3M = 0, 1, 2, 3, 4
 PRECISIONS = {"c64": TNC_C64, "f16_4m": TNC_F16_4M, "f16_3m": TNC_F16_3M, "bf16_4m": TNC_BF16_4M,
@@ -176,7 +178,12 @@ def tnc_network_create(ranks, labels, data_c128, n_qubits, output_labels):
     dp = None
     if data_c128 is not None:
         d = np.ascontiguousarray(data_c128, dtype=np.float64)
+        need = 2 * sum(1 << int(x) for x in r if 0 <= int(x) <= 30)
+        if d.size != need:
+            raise ValueError(f"data_c128 holds {d.size} doubles, the ranks need {need}")
         dp = d.ctypes.data_as(c_double_p)
+    if int(np.sum(r)) != len(lab):
+        raise ValueError("labels must hold sum(ranks) entries")
     o, op = _i32(output_labels)
     h = vp()
     _check(lib.tnc_network_create(len(r), rp, lp, dp, int(n_qubits), op, ctypes.byref(h)))

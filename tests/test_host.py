@@ -57,7 +57,7 @@ def test_hyperedges_are_planned_and_lonely_labels_summed():
     label until its last holder) and refused by the search; a label held by
     one tensor that is not an output is summed at creation."""
     # tensors: X[h, a], Y[h, b], W[h, c]; outputs a, b, c; hyperedge h
-    data = np.arange(1, 13, dtype=np.float64)
+    data = np.arange(1, 25, dtype=np.float64)
     h = T.tnc_network_create([2, 2, 2], [0, 1, 0, 2, 0, 3], data, 3, [1, 2, 3])
     with pytest.raises(T.TncError) as e:
         T.tnc_search(h, 3, [0, 1, 2], 30, restarts=1, seed=0)
