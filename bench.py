@@ -345,6 +345,25 @@ def cpu_baseline_codec(cpu_seconds):
                       f"{reps_cpu} rounds in {dt:.1f} s"}
 
 
+def path_roofline(T, plan, dtype_key, seconds_per_slice):
+    """Path-level roofline time per slice, T_roof = sum over the slice's steps
+    of max(F_t / P_mfma, B_t / 8 TB/s) with the permutes HBM-bound beside
+    them, against the measured time per slice."""
+    info = T.tnc_plan_info(plan)
+    n = info["n_steps"]
+    st = T.tnc_plan_steps(plan, n)
+    peak = PEAK[dtype_key] * 1e12
+    bw = HBM_GBS * 1e9
+    t = 0.0
+    for i in range(n):
+        if st["dep"][i]:
+            t += max(st["flops"][i] / peak, st["bytes"][i] / bw)
+    t += info["permute_bytes_per_slice"] / bw
+    return {"t_roof_s_per_slice": t, "t_measured_s_per_slice": seconds_per_slice,
+            "frac": round(t / seconds_per_slice, 4),
+            "note": "slice-dependent steps; GEMM bytes = A + B + C at the storage size, permutes at 8 TB/s"}
+
+
 def roofline_entry(fam, dtype_key):
     name, d = max(fam.items(), key=lambda kv: kv[1]["ms"])
     sec = d["ms"] * 1e-3
@@ -365,6 +384,169 @@ def roofline_entry(fam, dtype_key):
                              "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 2)} for k, v in fam.items()}}
 
 
+# ------------------------------------------------------------------ step microbenchmark
+
+def microbench(torch, T, forms=("f16_4m", "c64"), count=200, cpu_seconds=10.0):
+    """The 200 seeded pairwise contractions (rank 20-34 operands, 4-16 reduced
+    labels, 0-6 batch labels, random label orders) through tnc_contract, one
+    launch each after a warm launch: GEMM TFLOP/s (algorithmic 8 B M N K) and
+    permute GB/s (2 x the permuted tensor's bytes) per case, summarised per
+    form.  Cases whose working set does not fit the workspace at a form's
+    entry size are skipped for that form (reported)."""
+    from workloads import contractions as wc
+    cs = wc.cases(count)
+    free, _ = torch.cuda.mem_get_info()
+    ws_bytes = int(min(free - (24 << 30), 120 << 30))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda:0")
+    ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    gen = torch.Generator(device="cuda:0").manual_seed(5)
+    out = {}
+    for prec in forms:
+        es = 8 if prec == "c64" else 4
+        dk = DKEY[prec]
+        rows, skipped = [], 0
+        t_start = time.perf_counter()
+        for c in cs:
+            na, nb, nc = c.elems()
+            # operands + result on the device; permuted copies in the workspace
+            if es * (na + nb + nc) > free - ws_bytes - (16 << 30) or 2 * es * (na + nb + nc) > ws_bytes:
+                skipped += 1
+                continue
+            dt = torch.complex64 if prec == "c64" else torch.int32
+            A = torch.empty(na, dtype=dt, device="cuda:0")
+            B = torch.empty(nb, dtype=dt, device="cuda:0")
+            C = torch.empty(nc, dtype=dt, device="cuda:0")
+            for X, sc in ((A, 2.0 ** (-c.k / 2)), (B, 1.0)):
+                ri = torch.view_as_real(X) if prec == "c64" else X.view(torch.float16 if dk == "f16" else torch.bfloat16)
+                ri.normal_(0.0, sc * 0.7071, generator=gen)
+            torch.cuda.synchronize()
+            T.tnc_contract(ctx, prec, A, c.a_labels, B, c.b_labels, C, c.c_labels, scale_log2=0)
+            times, _ = T.tnc_contract(ctx, prec, A, c.a_labels, B, c.b_labels, C, c.c_labels, scale_log2=0)
+            fl = 8.0 * 2.0 ** (c.b + c.m + c.n + c.k)
+            pa, pb, gm, pc = times
+            rows.append({"seed": c.seed, "mnkb": [c.m, c.n, c.k, c.b], "gemm_ms": gm, "tflops": fl / (gm * 1e9),
+                         "perm_ms": [pa, pb, pc], "perm_bytes": [2.0 * es * na, 2.0 * es * nb, 2.0 * es * nc],
+                         "flops": fl})
+            del A, B, C
+        torch.cuda.empty_cache()
+        tf = np.array([r["tflops"] for r in rows])
+        g_ms = sum(r["gemm_ms"] for r in rows)
+        g_fl = sum(r["flops"] for r in rows)
+        # a permute that ran: more than 20 us (the events around a skipped permute read a few us)
+        pm = [(b, t) for r in rows for b, t in zip(r["perm_bytes"], r["perm_ms"]) if t > 0.02]
+        p_gbs = sum(b for b, _ in pm) / max(sum(t for _, t in pm) * 1e-3, 1e-12) / 1e9
+        big = [r for r in rows if r["flops"] >= 1e13]
+        out[prec] = {"cases": len(rows), "skipped": skipped,
+                     "gemm_tflops_aggregate": round(g_fl / (g_ms * 1e9), 2),
+                     "gemm_frac_of_peak_aggregate": round(g_fl / (g_ms * 1e9) / PEAK[dk], 4),
+                     "gemm_tflops_median": round(float(np.median(tf)), 2),
+                     "gemm_tflops_max": round(float(tf.max()), 2),
+                     "gemm_tflops_median_cases_over_1e13_flops": round(float(np.median([r["tflops"] for r in big])), 2)
+                     if big else None,
+                     "permutes": len(pm), "permute_gbs_aggregate": round(p_gbs, 1),
+                     "permute_frac_of_hbm": round(p_gbs / HBM_GBS, 4),
+                     "seconds": round(time.perf_counter() - t_start, 1)}
+        log(f"microbench {prec}: {out[prec]}")
+    T.tnc_destroy(ctx)
+    del ws
+    # the oracle beside it: one mid-size case through numpy (BLAS), bounded
+    from oracle import pairwise
+    model, threads = host_cpu()
+    c = min((c for c in cs if c.b == 0), key=lambda c: abs(8.0 * 2.0 ** (c.m + c.n + c.k) - 2e10))
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=(2,) * len(c.a_labels)) + 1j * rng.normal(size=(2,) * len(c.a_labels))
+    b = rng.normal(size=(2,) * len(c.b_labels)) + 1j * rng.normal(size=(2,) * len(c.b_labels))
+    fl = 8.0 * 2.0 ** (c.b + c.m + c.n + c.k)
+    t0, reps = time.perf_counter(), 0
+    while time.perf_counter() - t0 < cpu_seconds:
+        pairwise.contract_pair(a, c.a_labels, b, c.b_labels, c.c_labels)
+        reps += 1
+    dt = time.perf_counter() - t0
+    cpu = {"value": round(fl * reps / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle", "cpu": model,
+           "sample": f"oracle pairwise contraction of case {c.seed} (2^{c.m} x 2^{c.n} x 2^{c.k}, random label "
+                     f"orders), {reps} runs in {dt:.1f} s"}
+    return {"metric": "pairwise contraction microbenchmark (200 seeded cases)", "unit": "TFLOP/s",
+            "forms": out, "cpu_baseline": cpu}
+
+
+# ------------------------------------------------------------------ learned cost model study
+
+def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3)):
+    """Step timings measured by the engine on random 12- to 30-qubit circuits
+    under every form train the step-time MLP on the GPU; its held-out error is
+    compared with the FLOP model's (one fitted scale), and the path search for
+    the 30-qubit circuit is run under each model: the chosen paths' measured
+    block times decide what the learned model gains."""
+    from oracle import mlp as omlp
+    from paper_2407_00769_amd import costmodel
+    free, _ = torch.cuda.mem_get_info()
+    ws = torch.empty(int(min(free - (16 << 30), 32 << 30)), dtype=torch.uint8, device="cuda:0")
+    ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    circs = []
+    for i, (r, c, cyc) in enumerate([(3, 4, 8), (4, 4, 10), (4, 5, 10), (5, 5, 12), (4, 6, 12), (5, 6, 10),
+                                     (5, 6, 14), (4, 5, 14), (5, 5, 8), (3, 6, 12), (4, 4, 14), (5, 6, 12)]):
+        sites, cp = workloads.rect_grid(r, c)
+        circs.append(workloads.random_circuit(sites, cp, cyc, 100 + i))
+    t0 = time.perf_counter()
+    X, y, fl = costmodel.collect(ctx, circs, ["c64", "f16_4m", "f16_3m", "bf16_4m", "bf16_3m"], caps=[14, 18, 22],
+                                 open_counts=[4, 8], restarts=2, seed=1)
+    t_collect = time.perf_counter() - t0
+    n = len(y)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(n)
+    tr, te = perm[: int(0.8 * n)], perm[int(0.8 * n):]
+    t0 = time.perf_counter()
+    loss = T.tnc_mlp_train(ctx, X[tr], y[tr], epochs=60, batch=256, lr=2e-3, seed=7)
+    t_train = time.perf_counter() - t0
+    pred = T.tnc_mlp_predict(ctx, X[te])
+    cfit = costmodel.flop_model_fit(fl[tr], y[tr])
+    base = costmodel.flop_model_predict(fl[te], cfit)
+    err_mlp = np.abs(pred - y[te])
+    err_flop = np.abs(base - y[te])
+    # the oracle's FP64 trainer on one epoch of the same rows (CPU, timed)
+    t0 = time.perf_counter()
+    omlp.adam_train(X[tr].astype(np.float64), y[tr].astype(np.float64), 1, 256, 2e-3, 7)
+    t_cpu_epoch = time.perf_counter() - t0
+    # search the 30-qubit circuit under each model and time the chosen paths
+    T.tnc_costmodel_use(ctx)
+    c30 = workloads.config_circuit(2)
+    st = workloads.tn_structure(c30)
+    r, l, d, o = cn.network_arrays(c30, st)
+    net = T.tnc_network_create(r, l, d, c30.n_qubits, o)
+    open_q = list(range(20, 30))
+    bits = workloads.prefix_bitstrings(30, open_q, 1024, 3)
+    runs = []
+    for seed in seeds:
+        rec = {"seed": seed}
+        for model, name in ((0, "flop"), (1, "mlp")):
+            ts = time.perf_counter()
+            ssa, sl, lc = T.tnc_search(net, len(r), open_q, 22, cost_model=model, restarts=restarts, seed=seed)
+            t_search = time.perf_counter() - ts
+            plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
+            nsl = 1 << len(sl)
+            T.tnc_execute(plan, bits, 0, nsl)
+            best = min(T.tnc_execute(plan, bits, 0, nsl)[1]["seconds"] for _ in range(5))
+            rec[name] = {"block_ms": round(best * 1e3, 3), "sliced": len(sl), "log2_flops": round(lc, 3),
+                         "search_s": round(t_search, 2)}
+            T.tnc_plan_destroy(plan)
+        rec["gain"] = round(rec["flop"]["block_ms"] / rec["mlp"]["block_ms"], 4)
+        runs.append(rec)
+        log(f"costmodel seed {seed}: {rec}")
+    T.tnc_costmodel_use(None)
+    T.tnc_network_destroy(net)
+    T.tnc_destroy(ctx)
+    gains = [x["gain"] for x in runs]
+    return {"metric": "learned step-cost model: held-out error and measured gain of MLP-steered paths",
+            "rows": int(n), "collect_s": round(t_collect, 1), "train_s": round(t_train, 2), "train_loss": loss,
+            "heldout_median_abs_log2_err": {"mlp": round(float(np.median(err_mlp)), 4),
+                                            "flop": round(float(np.median(err_flop)), 4)},
+            "heldout_mape": {"mlp": round(float(np.mean(np.abs(2.0 ** err_mlp - 1))), 4),
+                             "flop": round(float(np.mean(np.abs(2.0 ** err_flop - 1))), 4)},
+            "search_30q": runs, "gain_geomean": round(float(np.exp(np.mean(np.log(gains)))), 4),
+            "cpu_baseline": {"value": round(t_cpu_epoch, 2), "unit": "s per epoch", "cores": host_cpu()[1],
+                             "kind": "oracle", "sample": f"oracle FP64 MLP training, one epoch of {len(tr)} rows"}}
+
+
 # ------------------------------------------------------------------ CPU baselines (the oracle)
 
 def cpu_baseline_sv(c, block_flops, n_slices, seconds_target):
@@ -372,6 +554,7 @@ def cpu_baseline_sv(c, block_flops, n_slices, seconds_target):
     the whole circuit (it produces every amplitude of the block)."""
     from oracle import statevector
     threads = statevector.threads()
+    model, _ = host_cpu()
     n_g = len(c.gates)
     t0 = time.perf_counter()
     statevector.simulate(c, stop=2)
@@ -382,16 +565,41 @@ def cpu_baseline_sv(c, block_flops, n_slices, seconds_target):
     t_s = time.perf_counter() - t0
     t_full = t_s * n_g / g
     return {"value": round(block_flops / t_full / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu": model,
             "sample": f"FP64 state vector (2^{c.n_qubits} amplitudes) over the first {g} of {n_g} gates in "
                       f"{t_s:.1f} s, scaled to all gates: {t_full:.1f} s for the {n_slices}-slice block; value = "
                       f"the block's algorithmic contraction flops / that time",
             "seconds_per_slice": t_full / n_slices}
 
 
+def host_cpu():
+    """(CPU model, BLAS threads numpy uses) of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = os.cpu_count() or 1
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [d["num_threads"] for d in threadpool_info() if d.get("user_api") == "blas"]
+        if blas:
+            threads = max(blas)
+    except Exception:
+        pass
+    return model, threads
+
+
 def cpu_baseline_einsum(flops_per_slice, seconds_target):
-    """FP64 pairwise contraction of the oracle (numpy complex128 einsum) timed
-    on a representative step shape; the per-slice time is an estimate."""
+    """FP64 pairwise contraction of the oracle (numpy complex128 einsum, which
+    reduces a plain pair to a BLAS matrix product on all host cores) timed on
+    a representative step shape; the per-slice time is an estimate."""
     from oracle import pairwise
+    model, threads = host_cpu()
     rng = np.random.default_rng(0)
     # a stem-like step: C has 2^13 x 2^9 entries, 2^10 reduced (3.4e10 flops)
     la, lb, lc = list(range(0, 23)), list(range(13, 32)), list(range(0, 13)) + list(range(23, 32))
@@ -405,11 +613,11 @@ def cpu_baseline_einsum(flops_per_slice, seconds_target):
         reps += 1
     dt = time.perf_counter() - t0
     rate = fl * reps / dt
-    return {"value": round(rate / 1e12, 6), "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle pairwise contraction (numpy complex128 einsum, one thread: numpy's einsum "
-                      f"kernel does not use BLAS) of a 2^13 x 2^9 x 2^10 step, "
-                      f"{reps} runs in {dt:.1f} s = {rate / 1e9:.1f} GFLOP/s; estimated "
-                      f"{flops_per_slice / rate:.0f} s per slice (no full oracle exists for 53 qubits)",
+    return {"value": round(rate / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu": model,
+            "sample": f"oracle pairwise contraction (numpy complex128, BLAS zgemm on {threads} threads, {model}) "
+                      f"of a 2^13 x 2^9 x 2^10 step, {reps} runs in {dt:.1f} s = {rate / 1e9:.1f} GFLOP/s; "
+                      f"estimated {flops_per_slice / rate:.0f} s per slice (no full oracle exists for 53 qubits)",
             "seconds_per_slice": flops_per_slice / rate}
 
 
@@ -429,6 +637,10 @@ def main():
                     help="only measure the low-precision exchange codec (its own JSON line)")
     ap.add_argument("--codec-study", action="store_true",
                     help="only run the single-step quantization study on the 30-qubit path (its own JSON line)")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only run the 200-case pairwise contraction microbenchmark (its own JSON line)")
+    ap.add_argument("--costmodel", action="store_true",
+                    help="only run the learned cost-model study (its own JSON line)")
     ap.add_argument("--postselect", action="store_true",
                     help="only run the top-1 post-selection study on the 30-qubit path (its own JSON line)")
     args = ap.parse_args()
@@ -446,6 +658,13 @@ def main():
     from paper_2407_00769_amd import _tnc as T
     if args.codec:
         print(json.dumps(codec_bench(torch, T)), flush=True)
+        return
+    if args.microbench:
+        print(json.dumps(microbench(torch, T)), flush=True)
+        return
+    if args.costmodel:
+        from paper_2407_00769_amd import circuit_network as cn
+        print(json.dumps(costmodel_study(torch, T, cn, workloads)), flush=True)
         return
     if args.postselect:
         from paper_2407_00769_amd import circuit_network as cn
@@ -529,6 +748,7 @@ def main():
     fam = timed_kernels(T, main_r["plan"], bits, 0, min(w["per_step"], 1 << len(w["sliced"])), dkey)
     roof = roofline_entry(fam, dkey)
     roof["traffic"] = measured_traffic(roof["kernel"], f"{w['name']}_{args.prec}")
+    roof["path"] = path_roofline(T, main_r["plan"], dkey, main_r["seconds"] / main_r["slices"])
 
     cpu = None
     if not args.no_cpu:

@@ -279,6 +279,13 @@ int tnc_contract(tnc_ctx *ctx, tnc_precision prec, const void *A, int32_t a_rank
  * context's cost model. */
 int tnc_mlp_train(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32_t epochs,
                   int32_t batch, float lr, uint64_t seed, float *loss_out);
+/* Continue from the current weights with `steps` full-batch Adam steps on
+ * the n rows (host arrays as in tnc_mlp_train), from fresh moments (m = v = 0,
+ * step count 0): beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, as
+ * tnc_mlp_train takes per minibatch.  loss_out (host, may be NULL): the mean
+ * squared error after the last step.  The weights become the cost model. */
+int tnc_mlp_adam(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32_t steps, float lr,
+                 float *loss_out);
 /* Predict n rows (host in, host out). */
 int tnc_mlp_predict(tnc_ctx *ctx, int64_t n, const float *x, float *y_out);
 /* One forward + backward pass on n rows with the current weights: loss (MSE)

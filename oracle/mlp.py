@@ -5,7 +5,10 @@ elementwise by IN_SCALE, then h1 = relu(W1 xs + b1) (128), h2 = relu(W2 h1 + b2)
 (128), out = W3 h2 + b3 (1).  Loss: mean over rows of (out - y)^2.
 Parameter vector order: W1 [128][8], b1, W2 [128][128], b2, W3 [1][128], b3.
 ``loss_and_grad`` is reverse-mode differentiation written out by hand;
-``numeric_grad`` is central finite differences (the pin).
+``numeric_grad`` is central finite differences (the pin).  ``adam_update`` is
+one step of Adam (Kingma and Ba, 2015), pinned by closed forms: under a
+constant gradient the bias-corrected moments equal g and g^2 exactly, and a
+two-step case is worked by hand.
 """
 from __future__ import annotations
 
@@ -85,9 +88,34 @@ def init(seed):
     return np.concatenate(parts)
 
 
+BETA1, BETA2, EPS = 0.9, 0.999, 1e-8
+
+
+def adam_update(p, m, v, g, t, lr):
+    """One Adam step (Kingma and Ba, Algorithm 1): first and second moment
+    averages, their bias corrections at step t (1-based), and the update
+    p - lr * mhat / (sqrt(vhat) + eps).  Returns the new (p, m, v)."""
+    m = BETA1 * m + (1.0 - BETA1) * g
+    v = BETA2 * v + (1.0 - BETA2) * g * g
+    mhat = m / (1.0 - BETA1 ** t)
+    vhat = v / (1.0 - BETA2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + EPS), m, v
+
+
+def adam_full_batch(p0, x, y, steps, lr):
+    """`steps` Adam steps on all rows from p0 and zero moments; returns
+    (parameters, loss after the last step)."""
+    p = np.array(p0, dtype=np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(1, steps + 1):
+        _, g = loss_and_grad(p, x, y)
+        p, m, v = adam_update(p, m, v, g, t, lr)
+    return p, loss(p, x, y)
+
+
 def adam_train(x, y, epochs, batch, lr, seed):
-    """Plain FP64 minibatch Adam (beta 0.9/0.999, eps 1e-8), for timing beside
-    the device trainer."""
+    """Plain FP64 minibatch Adam, for timing beside the device trainer."""
     p = init(seed)
     m = np.zeros_like(p)
     v = np.zeros_like(p)
@@ -100,7 +128,5 @@ def adam_train(x, y, epochs, batch, lr, seed):
             idx = order[r0:r0 + batch]
             _, g = loss_and_grad(p, x[idx], y[idx])
             t += 1
-            m = 0.9 * m + 0.1 * g
-            v = 0.999 * v + 0.001 * g * g
-            p -= lr * (m / (1 - 0.9 ** t)) / (np.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+            p, m, v = adam_update(p, m, v, g, t, lr)
     return p

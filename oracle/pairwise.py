@@ -2,7 +2,8 @@
 
 C[gamma] = sum over the reduced labels delta of A[alpha] * B[beta], with
 delta = alpha intersect beta minus gamma (labels kept in C that both operands
-hold are batch labels).  ``contract_pair`` is numpy.einsum in complex128;
+hold are batch labels).  ``contract_pair`` is numpy.einsum in complex128
+(a matrix product through BLAS where the labels allow);
 ``entry`` computes a single output element as an explicit FP64 dot product
 over the reduced labels (for spot checks of large contractions, where the
 operands are available only element by element).
@@ -22,7 +23,7 @@ def contract_pair(a, a_labels, b, b_labels, c_labels):
     sym = {l: _L[i] for i, l in enumerate(uni)}
     spec = "".join(sym[l] for l in a_labels) + "," + "".join(sym[l] for l in b_labels) + \
         "->" + "".join(sym[l] for l in c_labels)
-    return np.einsum(spec, np.asarray(a, np.complex128), np.asarray(b, np.complex128))
+    return np.einsum(spec, np.asarray(a, np.complex128), np.asarray(b, np.complex128), optimize=True)
 
 
 def entry(a_at, a_labels, b_at, b_labels, c_labels, c_values):

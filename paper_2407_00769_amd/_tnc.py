@@ -107,6 +107,8 @@ _SIGS = {
                                     vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_double_p, c_float_p]),
     "tnc_mlp_train": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_float, ctypes.c_uint64, c_float_p]),
+    "tnc_mlp_adam": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, ctypes.c_int32, ctypes.c_float,
+                                    c_float_p]),
     "tnc_mlp_predict": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p]),
     "tnc_mlp_grad": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, c_float_p, c_float_p]),
     "tnc_mlp_param_count": (ctypes.c_int64, []),
@@ -357,6 +359,14 @@ def tnc_mlp_train(ctx, x, y, epochs, batch, lr, seed):
     loss = ctypes.c_float(0)
     _check(lib.tnc_mlp_train(ctx, len(ya), xp, yp, int(epochs), int(batch), float(lr), ctypes.c_uint64(seed),
                              ctypes.byref(loss)))
+    return loss.value
+
+
+def tnc_mlp_adam(ctx, x, y, steps, lr):
+    xa, xp = _f32(x)
+    ya, yp = _f32(y)
+    loss = ctypes.c_float(0)
+    _check(lib.tnc_mlp_adam(ctx, len(ya), xp, yp, int(steps), float(lr), ctypes.byref(loss)))
     return loss.value
 
 

@@ -237,8 +237,11 @@ double mlp_path_cost(const Network &net, const std::vector<int> &ssa, const std:
                      const std::vector<int> &open_q) {
     tnc_ctx *ctx = g_cost_ctx;
     if (!ctx || !ctx->mlp || !ctx->mlp->trained) return -1.0;
-    Analysis an = analyze(net, (int)ssa.size() / 2, ssa.data(), (int)sliced.size(), sliced.data(), (int)open_q.size(),
-                          open_q.data(), TNC_F16_4M);
+    // the device path the plan would run: host absorption first, as in tnc_plan_create
+    Simplified sp = presimplify(net, (int)ssa.size() / 2, ssa.data(), (int)sliced.size(), sliced.data(),
+                                (int)open_q.size(), open_q.data(), host_rank_cap());
+    Analysis an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), (int)sliced.size(), sliced.data(),
+                          (int)open_q.size(), open_q.data(), TNC_F16_4M);
     const int64_t total = (int64_t)1 << an.n_sliced;
     const int64_t S = std::min<int64_t>(total, 64);   // slices batched per launch in the estimate
     std::vector<float> x;
@@ -315,6 +318,39 @@ extern "C" int tnc_mlp_train(tnc_ctx *ctx, int64_t n, const float *x, const floa
         HIP_CHECK(hipMemcpyAsync(&l, m->loss, sizeof(float), hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
         if (loss_out) *loss_out = l;
+        m->trained = true;
+    });
+}
+
+extern "C" int tnc_mlp_adam(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32_t steps, float lr,
+                            float *loss_out) {
+    return guard([&] {
+        if (!ctx || !x || !y) TNC_THROW(TNC_EINVAL, "NULL argument");
+        if (n < 1 || steps < 1) TNC_THROW(TNC_EINVAL, "n and steps must be positive");
+        HIP_CHECK(hipSetDevice(ctx->device));
+        hipStream_t st = ctx->stream;
+        Mlp *m = mlp_of(ctx);
+        ensure_rows(m, n);
+        HIP_CHECK(hipMemcpyAsync(m->x, x, n * F * sizeof(float), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(m->y, y, n * sizeof(float), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipMemsetAsync(m->m, 0, NPARAM * sizeof(float), st));
+        HIP_CHECK(hipMemsetAsync(m->v, 0, NPARAM * sizeof(float), st));
+        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+        for (int t = 1; t <= steps; t++) {
+            forward(m, m->x, nullptr, n, st);
+            backward(m, m->x, m->y, nullptr, n, st);
+            const float c1 = 1.f - std::pow(b1, (float)t), c2 = 1.f - std::pow(b2, (float)t);
+            hipLaunchKernelGGL(mlp_adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, m->params, m->grads,
+                               m->m, m->v, lr, b1, b2, eps, c1, c2);
+            HIP_CHECK(hipGetLastError());
+        }
+        forward(m, m->x, nullptr, n, st);
+        hipLaunchKernelGGL(mlp_loss_kernel, dim3(1), dim3(1), 0, st, m->y, (const int *)nullptr, n, m->out, m->loss);
+        float l = 0.f;
+        HIP_CHECK(hipMemcpyAsync(&l, m->loss, sizeof(float), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (loss_out) *loss_out = l;
+        m->step = steps;
         m->trained = true;
     });
 }

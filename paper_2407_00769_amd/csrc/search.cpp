@@ -13,7 +13,9 @@
 //   3. a re-run of the greedy order on the network with those labels removed,
 //      and slicing again, twice;
 //   4. across restarts, the (path, sliced labels) with the least cost: total
-//      FLOPs, or the learned step-time model's prediction when one is active.
+//      FLOPs, or the learned step-time model's prediction when one is active;
+//      the same cost also picks between a restart's greedy variants and
+//      decides whether a reconfigured tree is kept.
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -438,12 +440,25 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
         double best_flops = 0;
         const char *rc = getenv("TNC_SEARCH_RECONF");
         const int reconf_rounds = rc ? atoi(rc) : 8;
+        // Cost of a candidate (log2): total flops under the FLOP model, or the
+        // learned model's predicted device time of the path the plan would
+        // run; it picks between the greedy variants of a restart, decides
+        // whether a reconfigured tree replaces the current one, and ranks the
+        // restarts.
+        auto cost_of = [&](const Tree &tr, const Sliced &sv) -> double {
+            if (cost_model == 1) {
+                double c = mlp_path_cost(net, tr.ssa, sv.labels, open_q);
+                if (c > 0) return std::log2(c);
+            }
+            return sv.log2_total;
+        };
         for (int r = 0; r < restarts; r++) {
             double alpha = r == 0 ? 1.0 : ua(rng);
             double temp = r == 0 ? 0.0 : ut(rng) * ut(rng);
             std::vector<char> sl(L, 0);
             Tree t;
             Sliced s;
+            double s_cost = 0;
             for (int it = 0; it < 3; it++) {
                 std::vector<char> g2 = gone;
                 for (int l = 0; l < L; l++)
@@ -463,9 +478,11 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
                     }
                 }
                 Sliced sc = slice_tree(full, L, sliceable, log2_cap, sl);
-                if (it == 0 || sc.log2_total < s.log2_total) {
+                const double c = cost_of(full, sc);
+                if (it == 0 || c < s_cost) {
                     t = full;
                     s = sc;
+                    s_cost = c;
                 }
                 std::fill(sl.begin(), sl.end(), 0);
                 for (int l : s.labels) sl[l] = 1;
@@ -487,19 +504,17 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
                     Sliced s2 = slice_tree(t2, L, sliceable, log2_cap, sl2);
                     Sliced s3 = slice_tree(t2, L, sliceable, log2_cap, slv);
                     Sliced &pick = (s2.log2_total <= s3.log2_total) ? s2 : s3;
-                    if (pick.max_rank <= log2_cap && pick.log2_total < s.log2_total) {
+                    const double c2 = pick.max_rank <= log2_cap ? cost_of(t2, pick) : 1e300;
+                    if (c2 < s_cost) {
                         t = t2;
                         s = pick;
+                        s_cost = c2;
                     } else {
                         break;
                     }
                 }
             }
-            double cost = s.log2_total;
-            if (cost_model == 1) {
-                double c = mlp_path_cost(net, t.ssa, s.labels, open_q);
-                if (c > 0) cost = std::log2(c);
-            }
+            const double cost = s_cost;
             if (cost < best_cost) {
                 best_cost = cost;
                 best_ssa = t.ssa;

@@ -68,6 +68,32 @@ def test_device_gradients_match_fp64_oracle(T, ctx):
     np.testing.assert_allclose(pred, ref, rtol=1e-5, atol=1e-4)
 
 
+def test_adam_steps_match_fp64_oracle(T, ctx):
+    """A few full-batch Adam steps of the device trainer (FP32) against the
+    oracle's Adam (FP64, pinned by closed forms) from the same weights: the
+    per-parameter updates agree, which a wrong beta, bias correction or eps
+    would break (the first step alone is lr * sign(g) only with the bias
+    correction)."""
+    x, y = _rows(256, 5)
+    p0 = omlp.init(13).astype(np.float32)
+    p0[omlp.SIZES[0]:omlp.SIZES[0] + omlp.H] = 0.1
+    x64, y64, q0 = x.astype(np.float64), y.astype(np.float64), p0.astype(np.float64)
+    _, g0 = omlp.loss_and_grad(q0, x64, y64)
+    for steps, lr in ((1, 1e-3), (4, 1e-3), (4, 3e-2)):
+        T.tnc_mlp_set_params(ctx, p0)
+        loss = T.tnc_mlp_adam(ctx, x, y, steps, lr)
+        d_gpu = T.tnc_mlp_get_params(ctx).astype(np.float64) - q0
+        p_or, l_or = omlp.adam_full_batch(q0, x64, y64, steps, lr)
+        d_or = p_or - q0
+        big = np.abs(g0) > 1e-2 * np.max(np.abs(g0))
+        assert big.sum() > 1000
+        np.testing.assert_allclose(d_gpu[big], d_or[big], rtol=1e-2, atol=1e-3 * lr)
+        assert np.linalg.norm(d_gpu - d_or) <= 2e-2 * np.linalg.norm(d_or), steps
+        assert abs(loss - l_or) <= 1e-3 * abs(l_or) + 1e-6, (loss, l_or)
+        if steps == 1:   # bias-corrected first step: lr * g / (|g| + eps)
+            np.testing.assert_allclose(d_gpu[big], -lr * np.sign(g0[big]), rtol=1e-3)
+
+
 def test_training_is_deterministic_and_learns(T, ctx):
     x, y = _rows(2048, 2)
     l1 = T.tnc_mlp_train(ctx, x, y, epochs=20, batch=128, lr=3e-3, seed=7)
