@@ -15,9 +15,8 @@ Workloads:
   30q -- 5x6 grid, 14 cycles, 8 sliced labels; one step is the whole
      256-slice block; 1024 bitstrings sharing a 20-bit prefix.
 The primary form is FP16 storage with FP32-accumulated matrix-core GEMMs
-(4M); FP16-3M and BF16-4M run the same path; complex64 runs it with extra
-sliced labels where one slice would not fit (53q), normalised per original
-slice.
+(4M); FP16-3M, BF16-4M and complex64 run the same path (complex64 with one
+slice in flight, recomputing labels per pass if one slice would not fit).
 
 Prints one JSON line.  Extra keys: s_per_slice, forms, fidelity, roofline
 (dominant kernel family, HIP events around every launch of a step-timed
@@ -91,8 +90,8 @@ def setup_30q(args, T, cn, workloads):
 
 # ------------------------------------------------------------------ runs
 
-def run_form(T, ctx, w, prec, sliced, per_step, steps, warmup, torch):
-    plan = T.tnc_plan_create(ctx, w["net"], w["ssa"], sliced, w["open_q"], prec)
+def run_form(T, ctx, w, prec, sliced, per_step, steps, warmup, torch, recompute=None):
+    plan = T.tnc_plan_create(ctx, w["net"], w["ssa"], sliced, w["open_q"], prec, recompute=recompute)
     info = T.tnc_plan_info(plan)
     total = 1 << len(sliced)
     out = np.zeros(len(w["bits"]), dtype=np.complex128)
@@ -469,6 +468,79 @@ def microbench(torch, T, forms=("f16_4m", "c64"), count=200, cpu_seconds=10.0):
             "forms": out, "cpu_baseline": cpu}
 
 
+# ------------------------------------------------------------------ sparse state
+
+def sparse_study(torch, T, cn, workloads, n_bits=1024, cap=20, forms=("f16_4m", "c64"), sv=True):
+    """Uncorrelated bitstrings of the 30-qubit, 14-cycle circuit through a
+    sparse-state plan (Sec. 3.4.2): n_bits uniform random bitstrings share no
+    fixed bits; the path is found for the network with every output closed,
+    and each tensor keeps one block per distinct value of the bitstrings on
+    its qubits.  Reported: time and TFLOP/s per form, the work against one
+    closed contraction per bitstring, and parity against the oracle's FP64
+    state vector (all 2^30 amplitudes, on the host)."""
+    c = workloads.config_circuit(2)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    t0 = time.perf_counter()
+    ssa, sl, _ = T.tnc_search(net, len(r), [], cap, restarts=16, seed=1)
+    t_search = time.perf_counter() - t0
+    bits = workloads.uniform_bitstrings(30, n_bits, 7)
+    a_sp = T.tnc_plan_analyze_sparse(net, ssa, sl, bits, "f16_4m")
+    a_one = T.tnc_plan_analyze(net, ssa, sl, [], "f16_4m")
+    n_sl = 1 << len(sl)
+    flops_sparse = a_sp["flops_per_slice"] * n_sl + a_sp["flops_invariant"]
+    flops_each = (a_one["flops_per_slice"] * n_sl + a_one["flops_invariant"]) * n_bits
+    free, _ = torch.cuda.mem_get_info()
+    ws = torch.empty(int(min(free - (16 << 30), 96 << 30)), dtype=torch.uint8, device="cuda:0")
+    ctx = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    res = {}
+    outs = {}
+    for prec in forms:
+        plan = T.tnc_plan_create_sparse(ctx, net, ssa, sl, bits, prec)
+        info = T.tnc_plan_info(plan)
+        T.tnc_execute(plan, bits, 0, min(n_sl, info["slices_in_flight"]))   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, rep = T.tnc_execute(plan, bits, 0, n_sl)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        outs[prec] = out
+        res[prec] = {"seconds": round(dt, 4), "tflops": round(rep["flops"] / dt / 1e12, 2),
+                     "s_per_bitstring": dt / n_bits, "slices_in_flight": info["slices_in_flight"],
+                     "peak_bytes": info["peak_bytes"], "tune_seconds": round(info["tune_seconds"], 2)}
+        T.tnc_plan_destroy(plan)
+        log(f"sparse {prec}: {res[prec]}")
+    T.tnc_destroy(ctx)
+    del ws
+    ref, ref_kind, t_sv = None, None, None
+    if sv:
+        from oracle import statevector
+        t0 = time.perf_counter()
+        ref = statevector.amplitudes(c, bits)
+        t_sv = time.perf_counter() - t0
+        ref_kind = "oracle FP64 state vector (2^30 amplitudes, host)"
+    elif "c64" in outs:
+        ref, ref_kind = outs["c64"], "complex64 sparse-state run"
+    for prec, out in outs.items():
+        if ref is not None and not (ref_kind.startswith("complex64") and prec == "c64"):
+            b = ref.ravel()
+            res[prec]["fidelity"] = round(float(abs(np.vdot(b, out)) ** 2 / (np.vdot(b, b).real * np.vdot(out, out).real)), 9)
+            res[prec]["rel_l2"] = float(np.linalg.norm(out - b) / np.linalg.norm(b))
+            res[prec]["rel_max"] = float(np.max(np.abs(out - b)) / np.max(np.abs(b)))
+    T.tnc_network_destroy(net)
+    model, threads = host_cpu()
+    return {"metric": "sparse-state amplitudes of uncorrelated bitstrings", "unit": "s",
+            "workload": f"30-qubit 5x6 grid, 14 cycles; {n_bits} uniform random bitstrings (no shared bits); "
+                        f"path with every output closed, cap 2^{cap} entries, {len(sl)} sliced labels",
+            "search_seconds": round(t_search, 1), "flops_sparse": flops_sparse,
+            "flops_one_contraction_per_bitstring": flops_each, "work_ratio": round(flops_each / flops_sparse, 2),
+            "forms": res, "reference": ref_kind,
+            "cpu_baseline": None if t_sv is None else
+            {"value": round(t_sv, 1), "unit": "s", "cores": threads, "kind": "oracle", "cpu": model,
+             "sample": "oracle FP64 state vector of the whole 30-qubit circuit (every amplitude)"}}
+
+
 # ------------------------------------------------------------------ learned cost model study
 
 def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3)):
@@ -639,6 +711,8 @@ def main():
                     help="only run the single-step quantization study on the 30-qubit path (its own JSON line)")
     ap.add_argument("--microbench", action="store_true",
                     help="only run the 200-case pairwise contraction microbenchmark (its own JSON line)")
+    ap.add_argument("--sparse", action="store_true",
+                    help="only run the sparse-state study of uncorrelated bitstrings (its own JSON line)")
     ap.add_argument("--costmodel", action="store_true",
                     help="only run the learned cost-model study (its own JSON line)")
     ap.add_argument("--postselect", action="store_true",
@@ -661,6 +735,10 @@ def main():
         return
     if args.microbench:
         print(json.dumps(microbench(torch, T)), flush=True)
+        return
+    if args.sparse:
+        from paper_2407_00769_amd import circuit_network as cn
+        print(json.dumps(sparse_study(torch, T, cn, workloads)), flush=True)
         return
     if args.costmodel:
         from paper_2407_00769_amd import circuit_network as cn
@@ -690,10 +768,19 @@ def main():
     res = {}
     for prec in forms:
         if prec == "c64" and w["name"] == "53q":
-            # complex64 runs the path with extra sliced labels; time 4 of its slices
-            extra = len(w["sliced_c64"]) - len(w["sliced"])
-            r = run_form(T, ctx, w, prec, w["sliced_c64"], 4, 1, 1, torch)
-            r["per_original_slice"] = r["seconds"] / r["slices"] * (1 << extra)
+            # complex64 runs the same sliced path (one slice in flight); if one
+            # slice does not fit the workspace, labels are recomputed per pass
+            # (Sec. 3.4.1) until it does; time 2 slices after 2 warm ones
+            rec = None
+            try:
+                r = run_form(T, ctx, w, prec, w["sliced"], 2, 1, 1, torch)
+            except T.TncError as e:
+                if e.code != -2:
+                    raise
+                rec = T.tnc_recompute_path(w["net"], w["ssa"], w["sliced"], w["open_q"], 32)
+                r = run_form(T, ctx, w, prec, w["sliced"], 2, 1, 1, torch, recompute=rec)
+            r["recompute"] = None if rec is None else [int(x) for x in rec]
+            r["per_original_slice"] = r["seconds"] / r["slices"]
         else:
             r = run_form(T, ctx, w, prec, w["sliced"], w["per_step"], steps if prec == args.prec else 1,
                          args.warmup if prec == args.prec else 1, torch)
@@ -713,19 +800,14 @@ def main():
             ref_kind = "oracle (FP64 state vector, stored)"
     if ref is None and "c64" in res:
         if w["name"] == "53q":
-            extra = len(w["sliced_c64"]) - len(w["sliced"])
-            ref = np.zeros(len(bits), complex)
-            for j in range(1 << extra):
-                lo = j << len(w["sliced"])
-                o, _ = T.tnc_execute(res["c64"]["plan"], bits, lo, lo + 1)
-                ref += o
-            ref_kind = "complex64 GPU run of slice 0 (the sum of its 4 complex64 sub-slices); no full oracle for 53 qubits"
+            ref, _ = T.tnc_execute(res["c64"]["plan"], bits, 0, 1)
+            ref_kind = "complex64 GPU run of slice 0; no full oracle for 53 qubits"
         else:
             ref, _ = T.tnc_execute(res["c64"]["plan"], bits, 0, main_r["slices"])
             ref_kind = "complex64 GPU run"
 
     def fid(prec):
-        if ref is None or (prec == "c64" and w["name"] == "53q"):
+        if ref is None or prec == "c64":
             return None, None
         n = 1 if w["name"] == "53q" else 1 << len(w["sliced"])
         o, _ = T.tnc_execute(res[prec]["plan"], bits, 0, n)
@@ -740,7 +822,10 @@ def main():
                            "s_per_slice": r["per_original_slice"], "slices_timed": r["slices"],
                            "fidelity": None if f is None else round(f, 9), "rel_l2": rl, "replays": r["replays"],
                            "slices_in_flight": r["info"]["slices_in_flight"],
-                           "tune_seconds": round(r["info"]["tune_seconds"], 2)}
+                           "tune_seconds": round(r["info"]["tune_seconds"], 2),
+                           "peak_bytes": r["info"]["peak_bytes"]}
+        if r.get("recompute"):
+            forms_out[prec]["recompute_labels"] = r["recompute"]
     if "c64" in res and args.prec != "c64":
         forms_out[args.prec]["speedup_vs_c64"] = round(res["c64"]["per_original_slice"] / main_r["per_original_slice"], 3)
 

@@ -90,6 +90,8 @@ typedef struct {
     double tune_seconds;           /* host time spent timing kernel variants at plan time  */
     int32_t n_host_steps;          /* steps of the given path contracted on the host in     */
                                    /* FP64 before the device path (not in n_steps)          */
+    int32_t n_recompute;           /* recomputed labels (2^n_recompute passes per slice);   */
+                                   /* flops and bytes per slice count every pass            */
 } tnc_plan_stats;
 
 /* Results of one tnc_execute. */
@@ -180,6 +182,42 @@ int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const
                     int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
                     const int32_t *open_qubits, tnc_precision prec, int32_t max_slices_in_flight,
                     tnc_plan **out);
+/* Recomputation (paper Sec. 3.4.1): the large tensors of a slice are formed
+ * in parts instead of at once.  As tnc_plan_create, plus recompute_labels
+ * [n_recompute] (0..8 labels, neither sliced nor output labels), which are
+ * fixed per pass instead of per slice.  The steps whose sub-tree holds no
+ * recomputed label (the prefix) run once per slice and their results are kept;
+ * the rest (the suffix from the steps that bring those labels in) run once per
+ * pass, 2^n_recompute passes per slice, pass p setting recompute_labels[j] to
+ * bit j of p, and the passes add up to the slice's value.  A slice's result is
+ * the same sub-network sum as without recomputation (up to rounding order),
+ * so ranges of slices compose as before; only the suffix's tensors shrink,
+ * each by a factor 2 per recomputed label it holds.  tnc_plan_info then
+ * reports flops and bytes per slice over all passes and n_recompute. */
+int tnc_plan_create_recompute(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                              int32_t n_sliced, const int32_t *sliced_labels, int32_t n_recompute,
+                              const int32_t *recompute_labels, int32_t n_open, const int32_t *open_qubits,
+                              tnc_precision prec, int32_t max_slices_in_flight, tnc_plan **out);
+/* Sparse-state contraction of uncorrelated bitstrings (paper Sec. 3.4.2,
+ * "Tensor contraction during sparse state", Fig. sparse state): the
+ * amplitudes of bitstrings[n_bitstrings] (host; any values, duplicates
+ * allowed) in one contraction, whatever bits they share.  No output label is
+ * closed or left open: a tensor holding the output labels of qubit set Q is
+ * stored as one dense block per distinct value the bitstrings take on Q, and
+ * each step forms every result block from the operand blocks with the
+ * matching values -- a batched GEMM whose operands are gathered through index
+ * arrays (the multi-pair contraction of the figure, its first indexing
+ * scheme; the index is read inside the GEMM, so no gathered copy of an
+ * operand is made and no chunking is needed).  tnc_execute then takes exactly
+ * these bitstrings (TNC_EINVAL otherwise) and returns their amplitudes summed
+ * over the slice range.  Sliced labels as for tnc_plan_create.  Networks with
+ * hyperedges: TNC_EUNSUPPORTED.  The arena holds every tensor's blocks, so
+ * the path should bring the output labels in late (the sparse state of the
+ * final stage). */
+int tnc_plan_create_sparse(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                           int32_t n_sliced, const int32_t *sliced_labels, int64_t n_bitstrings,
+                           const uint64_t *bitstrings, tnc_precision prec, int32_t max_slices_in_flight,
+                           tnc_plan **out);
 int tnc_plan_destroy(tnc_plan *plan);
 int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats);
 
@@ -188,6 +226,29 @@ int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats);
 int tnc_plan_analyze(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
                      int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
                      const int32_t *open_qubits, tnc_precision prec, tnc_plan_stats *stats);
+
+/* tnc_plan_analyze with recomputed labels (as tnc_plan_create_recompute):
+ * peak_bytes is one slice's arena with the suffix at one pass. */
+int tnc_plan_analyze_recompute(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                               int32_t n_sliced, const int32_t *sliced_labels, int32_t n_recompute,
+                               const int32_t *recompute_labels, int32_t n_open, const int32_t *open_qubits,
+                               tnc_precision prec, tnc_plan_stats *stats);
+
+/* tnc_plan_analyze for a sparse-state plan (as tnc_plan_create_sparse):
+ * flops and bytes per slice over all blocks; peak_elems_per_slice is the
+ * largest tensor's entries over all its blocks. */
+int tnc_plan_analyze_sparse(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs, int32_t n_sliced,
+                            const int32_t *sliced_labels, int64_t n_bitstrings, const uint64_t *bitstrings,
+                            tnc_precision prec, tnc_plan_stats *stats);
+
+/* Choose recomputed labels for a sliced path (host only): while a tensor of
+ * one pass holds more than 2^log2_cap entries, add the label of a largest
+ * tensor (not an output label) whose recomputed suffix adds the least work
+ * over all passes.  recompute_out: host, capacity max_recompute (<= 8);
+ * n_out: host.  TNC_EINVAL when the cap needs more than max_recompute. */
+int tnc_recompute_path(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs, int32_t n_sliced,
+                       const int32_t *sliced_labels, int32_t n_open, const int32_t *open_qubits, double log2_cap,
+                       int32_t max_recompute, int32_t *recompute_out, int32_t *n_out);
 
 /* Host-only per-step description of a path (arrays as in tnc_plan_steps,
  * capacity n_steps, each may be NULL). */

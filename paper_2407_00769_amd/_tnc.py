@@ -52,7 +52,8 @@ class tnc_plan_stats(ctypes.Structure):
                 ("flops_per_slice", ctypes.c_double), ("flops_invariant", ctypes.c_double),
                 ("bytes_per_slice", ctypes.c_double), ("permute_bytes_per_slice", ctypes.c_double),
                 ("peak_bytes", ctypes.c_double), ("peak_elems_per_slice", ctypes.c_double),
-                ("tune_seconds", ctypes.c_double), ("n_host_steps", ctypes.c_int32)]
+                ("tune_seconds", ctypes.c_double), ("n_host_steps", ctypes.c_int32),
+                ("n_recompute", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,6 +82,19 @@ _SIGS = {
     "tnc_plan_create": (ctypes.c_int, [vp, vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
                                        ctypes.c_int32, c_int32_p, ctypes.c_int, ctypes.c_int32,
                                        ctypes.POINTER(vp)]),
+    "tnc_plan_create_recompute": (ctypes.c_int, [vp, vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
+                                                 ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p, ctypes.c_int,
+                                                 ctypes.c_int32, ctypes.POINTER(vp)]),
+    "tnc_plan_analyze_recompute": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
+                                                  ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p, ctypes.c_int,
+                                                  ctypes.POINTER(tnc_plan_stats)]),
+    "tnc_recompute_path": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p, ctypes.c_int32,
+                                          c_int32_p, ctypes.c_double, ctypes.c_int32, c_int32_p, c_int32_p]),
+    "tnc_plan_create_sparse": (ctypes.c_int, [vp, vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
+                                              ctypes.c_int64, c_u64_p, ctypes.c_int, ctypes.c_int32,
+                                              ctypes.POINTER(vp)]),
+    "tnc_plan_analyze_sparse": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p,
+                                               ctypes.c_int64, c_u64_p, ctypes.c_int, ctypes.POINTER(tnc_plan_stats)]),
     "tnc_plan_destroy": (ctypes.c_int, [vp]),
     "tnc_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(tnc_plan_stats)]),
     "tnc_plan_analyze": (ctypes.c_int, [vp, ctypes.c_int32, c_int32_p, ctypes.c_int32, c_int32_p, ctypes.c_int32,
@@ -219,15 +233,54 @@ def tnc_slice_path(net, ssa, open_qubits, log2_cap, sliced_in=(), max_sliced=62)
     return out[:n.value].copy()
 
 
-def tnc_plan_create(ctx, net, ssa, sliced, open_qubits, precision, max_slices_in_flight=0):
+def tnc_plan_create(ctx, net, ssa, sliced, open_qubits, precision, max_slices_in_flight=0, recompute=None):
+    """recompute: labels recomputed per pass (tnc_plan_create_recompute)."""
     s, sp = _i32(ssa)
     sl, slp = _i32(sliced)
     oq, op = _i32(open_qubits)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     h = vp()
-    _check(lib.tnc_plan_create(ctx, net, len(s) // 2, sp, len(sl), slp, len(oq), op, prec,
-                               int(max_slices_in_flight), ctypes.byref(h)))
+    if recompute is not None and len(recompute):
+        rc, rp = _i32(recompute)
+        _check(lib.tnc_plan_create_recompute(ctx, net, len(s) // 2, sp, len(sl), slp, len(rc), rp, len(oq), op, prec,
+                                             int(max_slices_in_flight), ctypes.byref(h)))
+    else:
+        _check(lib.tnc_plan_create(ctx, net, len(s) // 2, sp, len(sl), slp, len(oq), op, prec,
+                                   int(max_slices_in_flight), ctypes.byref(h)))
     return h
+
+
+def tnc_recompute_path(net, ssa, sliced, open_qubits, log2_cap, max_recompute=8):
+    s, sp = _i32(ssa)
+    sl, slp = _i32(sliced)
+    oq, op = _i32(open_qubits)
+    out = np.zeros(max(max_recompute, 1), dtype=np.int32)
+    n = ctypes.c_int32(0)
+    _check(lib.tnc_recompute_path(net, len(s) // 2, sp, len(sl), slp, len(oq), op, float(log2_cap), int(max_recompute),
+                                  out.ctypes.data_as(c_int32_p), ctypes.byref(n)))
+    return out[:n.value].copy()
+
+
+def tnc_plan_create_sparse(ctx, net, ssa, sliced, bitstrings, precision, max_slices_in_flight=0):
+    s, sp = _i32(ssa)
+    sl, slp = _i32(sliced)
+    b = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    h = vp()
+    _check(lib.tnc_plan_create_sparse(ctx, net, len(s) // 2, sp, len(sl), slp, len(b), b.ctypes.data_as(c_u64_p),
+                                      prec, int(max_slices_in_flight), ctypes.byref(h)))
+    return h
+
+
+def tnc_plan_analyze_sparse(net, ssa, sliced, bitstrings, precision) -> dict:
+    s, sp = _i32(ssa)
+    sl, slp = _i32(sliced)
+    b = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    st = tnc_plan_stats()
+    _check(lib.tnc_plan_analyze_sparse(net, len(s) // 2, sp, len(sl), slp, len(b), b.ctypes.data_as(c_u64_p), prec,
+                                       ctypes.byref(st)))
+    return st.as_dict()
 
 
 def tnc_plan_destroy(plan):
@@ -240,13 +293,18 @@ def tnc_plan_info(plan) -> dict:
     return st.as_dict()
 
 
-def tnc_plan_analyze(net, ssa, sliced, open_qubits, precision) -> dict:
+def tnc_plan_analyze(net, ssa, sliced, open_qubits, precision, recompute=None) -> dict:
     s, sp = _i32(ssa)
     sl, slp = _i32(sliced)
     oq, op = _i32(open_qubits)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     st = tnc_plan_stats()
-    _check(lib.tnc_plan_analyze(net, len(s) // 2, sp, len(sl), slp, len(oq), op, prec, ctypes.byref(st)))
+    if recompute is not None and len(recompute):
+        rc, rp = _i32(recompute)
+        _check(lib.tnc_plan_analyze_recompute(net, len(s) // 2, sp, len(sl), slp, len(rc), rp, len(oq), op, prec,
+                                              ctypes.byref(st)))
+    else:
+        _check(lib.tnc_plan_analyze(net, len(s) // 2, sp, len(sl), slp, len(oq), op, prec, ctypes.byref(st)))
     return st.as_dict()
 
 

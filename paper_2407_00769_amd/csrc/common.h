@@ -107,7 +107,12 @@ struct GemmShape {
     // the partial buffer was sized for (0: the launch's own count); a launch
     // over fewer slices keeps that factor, so it never needs more buffer
     int64_t split_slices = 0;
+    // sparse state: batch b reads block ia[b] of A and ib[b] of B (device
+    // arrays; NULL = block b); C's block is always b
+    const int32_t *ia = nullptr, *ib = nullptr;
 };
+__host__ __device__ inline int64_t a_block(const GemmShape &g, int64_t b) { return g.ia ? (int64_t)g.ia[b] : b; }
+__host__ __device__ inline int64_t b_block(const GemmShape &g, int64_t b) { return g.ib ? (int64_t)g.ib[b] : b; }
 
 // Scale bookkeeping of the 16-bit forms, per tensor and slice.
 struct ScaleRefs {
@@ -182,7 +187,7 @@ void launch_tensor_max(Dtype dt, const void *x, int64_t n, int S, int64_t slice_
                        uint32_t *max_out, hipStream_t st);
 void launch_accumulate(Dtype dt, const void *R, int rank, int S, int64_t slice_stride,
                        const double *expR, int n_exp_stride, int64_t nbits, const uint64_t *d_bits,
-                       const int *d_qubit_of_bit, double *acc, hipStream_t st);
+                       const int *d_qubit_of_bit, double *acc, hipStream_t st, const int32_t *d_map = nullptr);
 
 // Bits of an LDS-tiled permute.  The tile is the union T of the w lowest
 // destination bits and the destination bits that hold the w lowest source
@@ -212,9 +217,13 @@ struct LeafDesc {
     int64_t slice_stride[kMaxLeafRank];  // source stride of sliced label j
     int slice_bit[kMaxLeafRank];         // bit of the slice id that sets sliced label j
     int rank, n_sliced, n_slices, max_slot, slot_stride, pad_;
+    // sparse state: nd blocks, block d taken at element offset spoff[sp_base + d]
+    int64_t sp_base;
+    int nd, pad2_;
 };
 void launch_gather_leaves_impl(Dtype dt, int n_leaves, const LeafDesc *d_desc, const int64_t *d_params,
                                const void *leafdata, uint8_t *arena, uint32_t *maxw, double *expw,
-                               int group_base, int S, hipStream_t st);
+                               int64_t group_base, int S, hipStream_t st, const int64_t *spoff = nullptr,
+                               int nd_max = 1);
 
 }  // namespace tnc

@@ -175,7 +175,7 @@ static void free_plan_device(tnc_plan *p) {
     p->graphs.clear();
     void *ptrs[] = {p->d_leafdata, p->d_desc, p->d_maxw,  p->d_expw,  p->d_shift, p->d_growth, p->d_flags,
                     p->d_params,   p->d_bits, p->d_acc,   p->d_qob,   p->d_part,  p->d_codes,  p->d_qscale,
-                    p->d_qzero};
+                    p->d_qzero,    p->d_spoff, p->d_idx,  p->d_map};
     for (void *q : ptrs)
         if (q) hipFree(q);
 }
@@ -194,8 +194,9 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
     p->n_qubits = net.n_qubits;
     p->output_labels = net.output_labels;
     p->leaf_orig_labels = net.labels;
-    for (int q = 0; q < net.n_qubits; q++)
-        if (an.fixed[net.output_labels[q]] == 1) p->closed_qubits.push_back(q);
+    if (!an.sparse)
+        for (int q = 0; q < net.n_qubits; q++)
+            if (an.fixed[net.output_labels[q]] == 1) p->closed_qubits.push_back(q);
     // slices in flight: as many as fit, at most the slice count
     int64_t n_slices_total = (int64_t)1 << an.n_sliced;
     int64_t cap = n_slices_total;
@@ -231,14 +232,18 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
         HIP_CHECK(hipStreamSynchronize(st));
         hipFree(tmp);
     }
-    // leaf descriptors: invariant first, then dependent
-    std::vector<int> inv, dep;
-    for (int i = 0; i < nT; i++) (an.tensors[i].dep ? dep : inv).push_back(i);
+    // leaf descriptors: invariant first, then the slice prefix's, then the
+    // recomputed ones (gathered once per pass)
+    std::vector<int> inv, dep, inner;
+    for (int i = 0; i < nT; i++) (!an.tensors[i].dep ? inv : (an.tensors[i].inner ? inner : dep)).push_back(i);
     p->n_inv_leaves = (int)inv.size();
-    p->n_dep_leaves = (int)dep.size();
+    p->n_dep_leaves = (int)(dep.size() + inner.size());
+    p->n_inner_leaves = (int)inner.size();
     p->desc_of_leaf.assign(nT, -1);
     std::vector<int> order = inv;
     order.insert(order.end(), dep.begin(), dep.end());
+    order.insert(order.end(), inner.begin(), inner.end());
+    std::vector<int64_t> spoff;   // sparse state: element offset of every leaf block
     for (int i : order) {
         const TensorRec &t = an.tensors[i];
         LeafDesc d{};
@@ -264,8 +269,53 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
         d.n_slices = t.dep ? S : 1;
         d.max_slot = i * S;
         d.slot_stride = t.dep ? 1 : 0;
+        d.nd = 1;
+        d.sp_base = 0;
+        if (an.sparse) {
+            // block d of the leaf: its output labels at the qubit values of key d
+            d.nd = (int)t.nd;
+            d.sp_base = (int64_t)spoff.size();
+            d.dst_slice_stride *= t.nd;
+            for (uint64_t key : an.leaf_keys[i]) {
+                int64_t o = 0;
+                for (int j = 0; j < ro; j++) {
+                    const int l = orig[j];
+                    for (int q = 0; q < net.n_qubits; q++)
+                        if (net.output_labels[q] == l && ((key >> q) & 1)) o += (int64_t)1 << (ro - 1 - j);
+                }
+                spoff.push_back(o);
+            }
+            p->nd_max = std::max<int>(p->nd_max, (int)t.nd);
+        }
         p->desc_of_leaf[i] = (int)p->h_desc.size();
         p->h_desc.push_back(d);
+    }
+    if (an.sparse) {
+        if (p->nd_max > 65535) TNC_THROW(TNC_EUNSUPPORTED, "an input tensor with more than 65535 sparse blocks");
+        p->d_spoff = dev_alloc<int64_t>((int64_t)spoff.size());
+        HIP_CHECK(hipMemcpyAsync(p->d_spoff, spoff.data(), sizeof(int64_t) * spoff.size(), hipMemcpyHostToDevice, st));
+        // block index arrays of every step, one buffer
+        std::vector<int32_t> idx;
+        p->a_idx_off.assign(an.steps.size(), -1);
+        p->b_idx_off.assign(an.steps.size(), -1);
+        for (size_t k = 0; k < an.steps.size(); k++) {
+            const StepRec &rec = an.steps[k];
+            if (rec.a_mode == 2) {
+                p->a_idx_off[k] = (int64_t)idx.size();
+                idx.insert(idx.end(), rec.a_idx.begin(), rec.a_idx.end());
+            }
+            if (rec.b_mode == 2) {
+                p->b_idx_off[k] = (int64_t)idx.size();
+                idx.insert(idx.end(), rec.b_idx.begin(), rec.b_idx.end());
+            }
+        }
+        p->d_idx = dev_alloc<int32_t>((int64_t)idx.size());
+        if (!idx.empty())
+            HIP_CHECK(hipMemcpyAsync(p->d_idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice, st));
+        p->d_map = dev_alloc<int32_t>((int64_t)an.root_map.size());
+        HIP_CHECK(hipMemcpyAsync(p->d_map, an.root_map.data(), sizeof(int32_t) * an.root_map.size(),
+                                 hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipStreamSynchronize(st));
     }
     p->d_desc = dev_alloc<LeafDesc>((int64_t)p->h_desc.size());
     HIP_CHECK(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(LeafDesc) * p->h_desc.size(),
@@ -315,6 +365,46 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
     const char *ng = getenv("TNC_NO_GRAPH");
     // graphs are captured on the context's stream; the legacy null stream cannot be captured
     p->use_graph = !(ng && ng[0] == '1') && ctx->stream != nullptr;
+}
+
+// GEMM descriptor of step s as it runs in the arena: slice strides (per-slice
+// size of a slice-dependent operand, 0 for a shared one), the split-K buffer,
+// and, for sparse-state plans, which operand block every result block reads.
+static GemmShape plan_step_shape(const tnc_plan *p, int s) {
+    const Analysis &an = p->an;
+    const StepRec &rec = an.steps[s];
+    const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
+    const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank(), nz = (int64_t)1 << Z.rank();
+    GemmShape g = step_gemm(rec);
+    g.sA = A.dep ? na * A.nd : 0;
+    g.sB = B.dep ? nbb * B.nd : 0;
+    g.sC = nz * Z.nd;
+    g.part = p->d_part;
+    g.part_cap = p->part_bytes;
+    g.split_slices = rec.dep ? p->S : 1;   // the slice count d_part was sized for
+    if (an.sparse) {
+        if (rec.a_mode == 1) g.bA = 0;
+        if (rec.b_mode == 1) g.bB = 0;
+        if (rec.a_mode == 2) g.ia = p->d_idx + p->a_idx_off[s];
+        if (rec.b_mode == 2) g.ib = p->d_idx + p->b_idx_off[s];
+    }
+    return g;
+}
+
+// Bit permutation of operand X (`from` -> its stored order) for n_slices
+// slices: every slice's nd sparse blocks are permuted alike.
+static void permute_operand(const tnc_plan *p, const TensorRec &X, const std::vector<int> &from, const void *src,
+                            void *dst, int n_slices, hipStream_t st) {
+    const Dtype dt = p->an.dt;
+    const int64_t n = (int64_t)1 << X.rank();
+    const int64_t total = (int64_t)n_slices * X.nd;
+    const PermuteDesc d = make_permute(from, X.labels);
+    const int64_t es = elem_bytes(dt);
+    for (int64_t b0 = 0; b0 < total; b0 += 65535) {
+        const int cnt = (int)std::min<int64_t>(65535, total - b0);
+        launch_permute(dt, (const uint8_t *)src + b0 * n * es, (uint8_t *)dst + b0 * n * es, d, n, cnt, n, nullptr, n,
+                       st);
+    }
 }
 
 // ------------------------------------------------------------------ autotuner
@@ -411,17 +501,12 @@ double autotune_plan(tnc_plan *p) {
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
     auto t_start = std::chrono::steady_clock::now();
-    for (auto &rec : an.steps) {
+    for (size_t si = 0; si < an.steps.size(); si++) {
+        auto &rec = an.steps[si];
         const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
-        const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank(), nz = (int64_t)1 << Z.rank();
-        GemmShape g = step_gemm(rec);
-        g.sA = A.dep ? na : 0;
-        g.sB = B.dep ? nbb : 0;
-        g.sC = nz;
-        g.part = p->d_part;
-        g.part_cap = p->part_bytes;
+        const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank();
+        GemmShape g = plan_step_shape(p, (int)si);
         const int Sl = rec.dep ? p->S : 1;
-        g.split_slices = Sl;
         // the per-slice bookkeeping of the tuning launches holds S_t slices
         if (Sl > S_t) TNC_THROW(TNC_EINVAL, "internal: tuning launch covers more slices than its scratch holds");
         std::vector<int> cands;
@@ -452,7 +537,8 @@ double autotune_plan(tnc_plan *p) {
         void *pc = ws + Z.off;
         {
             // the arena holds no data yet: give the operands random values
-            const int64_t wa = (A.dep ? Sl : 1) * na * elem_bytes(dt) / 4, wb = (B.dep ? Sl : 1) * nbb * elem_bytes(dt) / 4;
+            const int64_t wa = (A.dep ? Sl : 1) * A.nd * na * elem_bytes(dt) / 4,
+                          wb = (B.dep ? Sl : 1) * B.nd * nbb * elem_bytes(dt) / 4;
             launch_fill_random(dt, (void *)pa, wa, 0x5eed0000u + (uint32_t)rec.a, st);
             launch_fill_random(dt, (void *)pb, wb, 0x5eed8000u + (uint32_t)rec.b, st);
         }
@@ -496,26 +582,34 @@ double autotune_plan(tnc_plan *p) {
 }
 }  // namespace
 
-extern "C" int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
-                               int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
-                               const int32_t *open_qubits, tnc_precision prec, int32_t max_slices_in_flight,
-                               tnc_plan **out) {
+static int create_plan(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                       int32_t n_sliced, const int32_t *sliced_labels, int32_t n_recompute,
+                       const int32_t *recompute_labels, int32_t n_open, const int32_t *open_qubits,
+                       int64_t n_sparse, const uint64_t *sparse_bits, tnc_precision prec, int32_t max_slices_in_flight,
+                       tnc_plan **out) {
     API_BEGIN
     REQUIRE(out, "out is NULL");
     *out = nullptr;
     REQUIRE(ctx && net, "ctx or net is NULL");
     REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
     REQUIRE(n_sliced == 0 || sliced_labels, "sliced_labels is NULL");
+    REQUIRE(n_recompute == 0 || recompute_labels, "recompute_labels is NULL");
     REQUIRE(n_open == 0 || open_qubits, "open_qubits is NULL");
     auto *p = new tnc_plan;
     p->ctx = ctx;
     try {
-        Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits,
-                                    host_rank_cap());
+        // a sparse-state plan keeps every output label (none is closed on the host)
+        std::vector<int32_t> all_q;
+        if (sparse_bits)
+            for (int q = 0; q < net->net.n_qubits; q++) all_q.push_back(q);
+        Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels,
+                                    sparse_bits ? (int)all_q.size() : n_open, sparse_bits ? all_q.data() : open_qubits,
+                                    host_rank_cap(), n_recompute, recompute_labels);
         p->plan_step_of = sp.plan_step_of;
         p->host_steps = sp.host_steps;
         p->an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), n_sliced, sliced_labels, n_open, open_qubits,
-                        prec);
+                        prec, n_recompute, recompute_labels, n_sparse, sparse_bits);
+        if (sparse_bits) p->sparse_bits.assign(sparse_bits, sparse_bits + n_sparse);
         build_plan(p, sp.net, max_slices_in_flight);
         p->tune_seconds = autotune_plan(p);
     } catch (...) {
@@ -525,6 +619,35 @@ extern "C" int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_s
     }
     *out = p;
     API_END
+}
+
+extern "C" int tnc_plan_create_recompute(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps,
+                                         const int32_t *ssa_pairs, int32_t n_sliced, const int32_t *sliced_labels,
+                                         int32_t n_recompute, const int32_t *recompute_labels, int32_t n_open,
+                                         const int32_t *open_qubits, tnc_precision prec, int32_t max_slices_in_flight,
+                                         tnc_plan **out) {
+    return create_plan(ctx, net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_recompute, recompute_labels, n_open,
+                       open_qubits, 0, nullptr, prec, max_slices_in_flight, out);
+}
+
+extern "C" int tnc_plan_create_sparse(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                                      int32_t n_sliced, const int32_t *sliced_labels, int64_t n_bitstrings,
+                                      const uint64_t *bitstrings, tnc_precision prec, int32_t max_slices_in_flight,
+                                      tnc_plan **out) {
+    if (n_bitstrings < 1 || !bitstrings) {
+        set_error("a sparse-state plan needs at least one bitstring");
+        return TNC_EINVAL;
+    }
+    return create_plan(ctx, net, n_steps, ssa_pairs, n_sliced, sliced_labels, 0, nullptr, 0, nullptr, n_bitstrings,
+                       bitstrings, prec, max_slices_in_flight, out);
+}
+
+extern "C" int tnc_plan_create(tnc_ctx *ctx, const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                               int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
+                               const int32_t *open_qubits, tnc_precision prec, int32_t max_slices_in_flight,
+                               tnc_plan **out) {
+    return tnc_plan_create_recompute(ctx, net, n_steps, ssa_pairs, n_sliced, sliced_labels, 0, nullptr, n_open,
+                                     open_qubits, prec, max_slices_in_flight, out);
 }
 
 extern "C" int tnc_plan_destroy(tnc_plan *plan) {
@@ -547,20 +670,108 @@ extern "C" int tnc_plan_info(const tnc_plan *plan, tnc_plan_stats *stats) {
     API_END
 }
 
-extern "C" int tnc_plan_analyze(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs, int32_t n_sliced,
-                                const int32_t *sliced_labels, int32_t n_open, const int32_t *open_qubits,
-                                tnc_precision prec, tnc_plan_stats *stats) {
+extern "C" int tnc_plan_analyze_recompute(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                                          int32_t n_sliced, const int32_t *sliced_labels, int32_t n_recompute,
+                                          const int32_t *recompute_labels, int32_t n_open, const int32_t *open_qubits,
+                                          tnc_precision prec, tnc_plan_stats *stats) {
     API_BEGIN
     REQUIRE(net && stats, "NULL argument");
     REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
+    REQUIRE(n_recompute == 0 || recompute_labels, "recompute_labels is NULL");
     Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits,
-                                host_rank_cap());
+                                host_rank_cap(), n_recompute, recompute_labels);
     Analysis an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), n_sliced, sliced_labels, n_open, open_qubits,
-                          prec);
+                          prec, n_recompute, recompute_labels);
     fill_stats(an, *stats);
     stats->n_host_steps = sp.host_steps;
     stats->slices_in_flight = 0;
     stats->peak_bytes = (double)plan_memory(an, 1, false);
+    API_END
+}
+
+extern "C" int tnc_plan_analyze_sparse(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                                       int32_t n_sliced, const int32_t *sliced_labels, int64_t n_bitstrings,
+                                       const uint64_t *bitstrings, tnc_precision prec, tnc_plan_stats *stats) {
+    API_BEGIN
+    REQUIRE(net && stats, "NULL argument");
+    REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
+    REQUIRE(n_bitstrings >= 1 && bitstrings, "a sparse-state plan needs at least one bitstring");
+    std::vector<int32_t> all_q;
+    for (int q = 0; q < net->net.n_qubits; q++) all_q.push_back(q);
+    Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, (int)all_q.size(), all_q.data(),
+                                host_rank_cap());
+    Analysis an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), n_sliced, sliced_labels, 0, nullptr, prec, 0,
+                          nullptr, n_bitstrings, bitstrings);
+    fill_stats(an, *stats);
+    stats->n_host_steps = sp.host_steps;
+    stats->slices_in_flight = 0;
+    stats->peak_bytes = (double)plan_memory(an, 1, false);
+    API_END
+}
+
+extern "C" int tnc_plan_analyze(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs, int32_t n_sliced,
+                                const int32_t *sliced_labels, int32_t n_open, const int32_t *open_qubits,
+                                tnc_precision prec, tnc_plan_stats *stats) {
+    return tnc_plan_analyze_recompute(net, n_steps, ssa_pairs, n_sliced, sliced_labels, 0, nullptr, n_open,
+                                      open_qubits, prec, stats);
+}
+
+extern "C" int tnc_recompute_path(const tnc_network *net, int32_t n_steps, const int32_t *ssa_pairs,
+                                  int32_t n_sliced, const int32_t *sliced_labels, int32_t n_open,
+                                  const int32_t *open_qubits, double log2_cap, int32_t max_recompute,
+                                  int32_t *recompute_out, int32_t *n_out) {
+    API_BEGIN
+    REQUIRE(net && n_out && (max_recompute == 0 || recompute_out), "NULL argument");
+    REQUIRE(n_steps == 0 || ssa_pairs, "ssa_pairs is NULL");
+    REQUIRE(max_recompute >= 0 && max_recompute <= 8, "max_recompute out of [0, 8]");
+    // Greedy, as the slicer: while a tensor of one pass has more than 2^cap
+    // entries, recompute the label of a largest tensor whose suffix adds the
+    // least work over all passes.
+    std::vector<int32_t> rec;
+    auto eval = [&](const std::vector<int32_t> &r, Analysis *keep) {
+        Simplified sp = presimplify(net->net, n_steps, ssa_pairs, n_sliced, sliced_labels, n_open, open_qubits,
+                                    host_rank_cap(), (int)r.size(), r.data());
+        Analysis an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), n_sliced, sliced_labels, n_open,
+                              open_qubits, TNC_F16_4M, (int)r.size(), r.data());
+        if (keep) *keep = std::move(an);
+        else {
+            tnc_plan_stats st;
+            fill_stats(an, st);
+            return st.flops_per_slice;
+        }
+        return 0.0;
+    };
+    std::vector<char> is_out(net->net.n_labels, 0);
+    for (int l : net->net.output_labels) is_out[l] = 1;
+    for (;;) {
+        Analysis an;
+        eval(rec, &an);
+        int mr = 0;
+        for (const auto &t : an.tensors) mr = std::max(mr, t.rank());
+        if (mr <= log2_cap) break;
+        if ((int)rec.size() >= max_recompute)
+            TNC_THROW(TNC_EINVAL, "the cap needs more than max_recompute recomputed labels");
+        std::vector<int> cand;
+        for (const auto &t : an.tensors)
+            if (t.rank() == mr)
+                for (int l : t.labels)
+                    if (!is_out[l] && std::find(cand.begin(), cand.end(), l) == cand.end()) cand.push_back(l);
+        double best = 1e300;
+        int bl = -1;
+        for (int l : cand) {
+            std::vector<int32_t> r = rec;
+            r.push_back(l);
+            const double f = eval(r, nullptr);
+            if (f < best) {
+                best = f;
+                bl = l;
+            }
+        }
+        if (bl < 0) TNC_THROW(TNC_EINVAL, "no label of the largest tensor can be recomputed");
+        rec.push_back(bl);
+    }
+    std::copy(rec.begin(), rec.end(), recompute_out);
+    *n_out = (int)rec.size();
     API_END
 }
 
@@ -587,33 +798,19 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
     const Dtype dt = an.dt;
     const int es = elem_bytes(dt);
     const int Sl = rec.dep ? S_g : 1;
-    const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank(), nz = (int64_t)1 << Z.rank();
+    const int64_t nz = (int64_t)1 << Z.rank();
     const void *pa = ws + A.off;
     const void *pb = ws + B.off;
     if (tm) HIP_CHECK(hipEventRecord(tm->e[0], st));
     if (rec.perm_a) {
-        if (!rec.hoist_a) {
-            PermuteDesc d = make_permute(rec.a_from, A.labels);
-            int Sa = A.dep ? S_g : 1;
-            launch_permute(dt, ws + A.off, ws + rec.scr_a, d, na, Sa, A.dep ? na : 0, nullptr, A.dep ? na : 0, st);
-        }
+        if (!rec.hoist_a) permute_operand(p, A, rec.a_from, ws + A.off, ws + rec.scr_a, A.dep ? S_g : 1, st);
         pa = ws + rec.scr_a;
     }
     if (rec.perm_b) {
-        if (!rec.hoist_b) {
-            PermuteDesc d = make_permute(rec.b_from, B.labels);
-            int Sb = B.dep ? S_g : 1;
-            launch_permute(dt, ws + B.off, ws + rec.scr_b, d, nbb, Sb, B.dep ? nbb : 0, nullptr, B.dep ? nbb : 0, st);
-        }
+        if (!rec.hoist_b) permute_operand(p, B, rec.b_from, ws + B.off, ws + rec.scr_b, B.dep ? S_g : 1, st);
         pb = ws + rec.scr_b;
     }
-    GemmShape g = step_gemm(rec);
-    g.sA = A.dep ? na : 0;
-    g.sB = B.dep ? nbb : 0;
-    g.sC = nz;
-    g.part = p->d_part;
-    g.part_cap = p->part_bytes;
-    g.split_slices = rec.dep ? p->S : 1;   // the slice count d_part was sized for
+    GemmShape g = plan_step_shape(p, s);
     (void)es;
     ScaleRefs sc{};
     if (dt != Dtype::C64) {
@@ -656,7 +853,7 @@ void enqueue_block(tnc_plan *p, int64_t nsl, int64_t nbits, hipStream_t st, bool
     launch_fill_f64(p->d_acc, 0.0, 2 * nbits, st);
     if (dt != Dtype::C64) launch_fill_u32(p->d_maxw, 0u, nslots, st);
     launch_gather_leaves_impl(dt, p->n_inv_leaves, p->d_desc, p->d_params, p->d_leafdata, p->ctx->ws, p->d_maxw,
-                              p->d_expw, 0, 1, st);
+                              p->d_expw, 0, 1, st, p->d_spoff, p->nd_max);
     StepTimer tm{};
     if (timed)
         for (auto &e : tm.e) HIP_CHECK(hipEventCreate(&e));
@@ -678,18 +875,12 @@ void enqueue_block(tnc_plan *p, int64_t nsl, int64_t nbits, hipStream_t st, bool
     for (int s = 0; s < (int)an.steps.size(); s++) {
         const StepRec &rec = an.steps[s];
         uint8_t *ws = p->ctx->ws;
-        if (rec.hoist_a) {
-            const TensorRec &A = an.tensors[rec.a];
-            launch_permute(dt, ws + A.off, ws + rec.scr_a, make_permute(rec.a_from, A.labels), (int64_t)1 << A.rank(),
-                           1, 0, nullptr, 0, st);
-        }
-        if (rec.hoist_b) {
-            const TensorRec &B = an.tensors[rec.b];
-            launch_permute(dt, ws + B.off, ws + rec.scr_b, make_permute(rec.b_from, B.labels), (int64_t)1 << B.rank(),
-                           1, 0, nullptr, 0, st);
-        }
+        if (rec.hoist_a) permute_operand(p, an.tensors[rec.a], rec.a_from, ws + an.tensors[rec.a].off, ws + rec.scr_a, 1, st);
+        if (rec.hoist_b) permute_operand(p, an.tensors[rec.b], rec.b_from, ws + an.tensors[rec.b].off, ws + rec.scr_b, 1, st);
     }
     const TensorRec &R = an.tensors[an.root];
+    const int n_outer_leaves = p->n_dep_leaves - p->n_inner_leaves;
+    const int64_t passes = (int64_t)1 << an.n_recompute;
     for (int64_t g0 = 0; g0 < nsl; g0 += S) {
         const int S_g = (int)std::min<int64_t>(S, nsl - g0);
         if (dt != Dtype::C64 && g0 > 0) {
@@ -697,13 +888,27 @@ void enqueue_block(tnc_plan *p, int64_t nsl, int64_t nbits, hipStream_t st, bool
             for (size_t t = 0; t < an.tensors.size(); t++)
                 if (an.tensors[t].dep) launch_fill_u32(p->d_maxw + (int64_t)t * S, 0u, S, st);
         }
-        launch_gather_leaves_impl(dt, p->n_dep_leaves, p->d_desc + p->n_inv_leaves, p->d_params, p->d_leafdata,
-                                  p->ctx->ws, p->d_maxw, p->d_expw, (int)g0, S_g, st);
+        // the slice prefix: once per group
+        launch_gather_leaves_impl(dt, n_outer_leaves, p->d_desc + p->n_inv_leaves, p->d_params, p->d_leafdata,
+                                  p->ctx->ws, p->d_maxw, p->d_expw, g0, S_g, st, p->d_spoff, p->nd_max);
         for (int s = 0; s < (int)an.steps.size(); s++)
-            if (an.steps[s].dep) run(s, S_g);
-        launch_accumulate(dt, p->ctx->ws + R.off, R.rank(), S_g, (int64_t)1 << R.rank(),
-                          dt == Dtype::C64 ? nullptr : p->d_expw + (int64_t)an.root * S, 1, nbits, p->d_bits, p->d_qob,
-                          p->d_acc, st);
+            if (an.steps[s].dep && !an.steps[s].inner) run(s, S_g);
+        // the recomputed suffix: once per pass; a pass's recomputed label
+        // values are the slice id bits above the sliced ones (the group's
+        // slice ids stay below 2^n_sliced, so adding them carries nothing)
+        for (int64_t pass = 0; pass < passes; pass++) {
+            if (dt != Dtype::C64 && pass > 0)
+                for (size_t t = 0; t < an.tensors.size(); t++)
+                    if (an.tensors[t].inner) launch_fill_u32(p->d_maxw + (int64_t)t * S, 0u, S, st);
+            launch_gather_leaves_impl(dt, p->n_inner_leaves, p->d_desc + p->n_inv_leaves + n_outer_leaves, p->d_params,
+                                      p->d_leafdata, p->ctx->ws, p->d_maxw, p->d_expw,
+                                      g0 + (pass << an.n_sliced), S_g, st, p->d_spoff, p->nd_max);
+            for (int s = 0; s < (int)an.steps.size(); s++)
+                if (an.steps[s].inner) run(s, S_g);
+            launch_accumulate(dt, p->ctx->ws + R.off, R.rank(), S_g, ((int64_t)1 << R.rank()) * R.nd,
+                              dt == Dtype::C64 ? nullptr : p->d_expw + (int64_t)an.root * S, 1, nbits, p->d_bits,
+                              p->d_qob, p->d_acc, st, p->d_map);
+        }
     }
     if (timed)
         for (auto &e : tm.e) hipEventDestroy(e);
@@ -722,6 +927,7 @@ extern "C" int tnc_plan_set_codec(tnc_plan *plan, int32_t step, int32_t kind, in
     }
     if (step >= 0 && plan->an.dt != Dtype::C64)
         TNC_THROW(TNC_EUNSUPPORTED, "the codec round trip applies to complex64 plans (float32 values)");
+    if (step >= 0 && plan->an.sparse) TNC_THROW(TNC_EUNSUPPORTED, "the codec round trip applies to dense plans");
     int64_t cb = 0, ng = 0;
     if (step >= 0) {
         // per-slice results sit nz complex values apart; the codec's vector
@@ -911,6 +1117,12 @@ extern "C" int tnc_execute(tnc_plan *p, int64_t n_bitstrings, const uint64_t *bi
     if (rep) *rep = tnc_report{};
     const int64_t nsl = slice_end - slice_begin;
     if (n_bitstrings == 0) return TNC_OK;
+    if (an.sparse) {
+        // a sparse-state plan computes the blocks of the bitstrings it was made for
+        REQUIRE(n_bitstrings == (int64_t)p->sparse_bits.size() &&
+                    std::equal(bitstrings, bitstrings + n_bitstrings, p->sparse_bits.begin()),
+                "a sparse-state plan takes exactly the bitstrings it was created with");
+    }
     // closed qubits: values must agree across the request
     std::vector<int> closed_val(p->n_qubits, 0);
     for (int q : p->closed_qubits) {
@@ -1034,7 +1246,8 @@ extern "C" int tnc_execute(tnc_plan *p, int64_t n_bitstrings, const uint64_t *bi
     HIP_CHECK(hipStreamSynchronize(st));
     if (rep) {
         double fl = 0;
-        for (auto &s : an.steps) fl += s.dep ? s.flops * (double)nsl : s.flops;
+        const double passes = std::ldexp(1.0, an.n_recompute);
+        for (auto &s : an.steps) fl += s.dep ? s.flops * (double)nsl * (s.inner ? passes : 1.0) : s.flops;
         rep->seconds = ms * 1e-3;
         rep->flops = fl;
         rep->slices = nsl;

@@ -49,7 +49,8 @@ struct tnc_plan {
     void *d_leafdata = nullptr;
     tnc::LeafDesc *d_desc = nullptr;   // invariant descriptors first, then dependent
     std::vector<tnc::LeafDesc> h_desc;
-    int n_inv_leaves = 0, n_dep_leaves = 0;
+    int n_inv_leaves = 0, n_dep_leaves = 0;   // dependent = prefix leaves, then recomputed ones
+    int n_inner_leaves = 0;                   // the recomputed (per-pass) leaves among the dependent ones
     std::vector<int> desc_of_leaf;
     uint32_t *d_maxw = nullptr;
     double *d_expw = nullptr;
@@ -72,6 +73,15 @@ struct tnc_plan {
     bool timing = false;
     std::vector<double> step_ms, perm_ms;
     std::vector<int> step_launches;
+    // sparse state: leaf block offsets, per-step block index arrays (one
+    // buffer; offsets per step, -1 = none), the root block of each requested
+    // bitstring, and the requested bitstrings themselves
+    int64_t *d_spoff = nullptr;
+    int nd_max = 1;
+    int32_t *d_idx = nullptr;
+    std::vector<int64_t> a_idx_off, b_idx_off;
+    int32_t *d_map = nullptr;
+    std::vector<uint64_t> sparse_bits;
     // exchange codec round trip applied to one step's result (complex64 plans)
     int codec_step = -1, codec_kind = 0, codec_group = 0;
     void *d_codes = nullptr;

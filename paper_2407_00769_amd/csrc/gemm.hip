@@ -88,8 +88,8 @@ __global__ void __launch_bounds__(256) gemm_naive_kernel(const W *__restrict__ A
     int shift = SCALE ? step_shift(sc, s) : 0;
     if (SCALE && blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
     const float scale = pow2_neg(shift);
-    const W *Ap = A + s * g.sA + b * g.bA;
-    const W *Bp = B + s * g.sB + b * g.bB;
+    const W *Ap = A + s * g.sA + a_block(g, b) * g.bA;
+    const W *Bp = B + s * g.sB + b_block(g, b) * g.bB;
     W *Cp = C + s * g.sC + b * g.bC;
     float mx = 0.f;
     const int64_t total = g.M * g.N;
@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(const W *__restrict__ 
     int shift = SCALE ? step_shift(sc, s) : 0;
     if (SCALE && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
     const float scale = pow2_neg(shift);
-    const W *Ap = A + s * g.sA + b * g.bA;
-    const W *Bp = B + s * g.sB + b * g.bB;
+    const W *Ap = A + s * g.sA + a_block(g, b) * g.bA;
+    const W *Bp = B + s * g.sB + b_block(g, b) * g.bB;
     W *Cp = C + s * g.sC + b * g.bC;
     const int nn = (int)((g.N - n0) < NN ? (g.N - n0) : NN);
     const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -263,8 +263,8 @@ __global__ void __launch_bounds__(256) gemm_thin_kernel(const W *__restrict__ A,
     int shift = SCALE ? step_shift(sc, s) : 0;
     if (SCALE && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
     const float scale = pow2_neg(shift);
-    const W *Ap = A + s * g.sA + b * g.bA;
-    const W *Bp = B + s * g.sB + b * g.bB;
+    const W *Ap = A + s * g.sA + a_block(g, b) * g.bA;
+    const W *Bp = B + s * g.sB + b_block(g, b) * g.bB;
     W *Cp = C + s * g.sC + b * g.bC;
     const int K = (int)g.K;
     for (int e = threadIdx.x; e < NN * KMAX; e += blockDim.x) {
@@ -520,8 +520,8 @@ __global__ void __launch_bounds__(64 * WM * WN)
         scale = pow2_neg(shift);
     }
 
-    const uint32_t *Ap = A + s * g.sA + b * g.bA;
-    const uint32_t *Bp = B + s * g.sB + b * g.bB;
+    const uint32_t *Ap = A + s * g.sA + a_block(g, b) * g.bA;
+    const uint32_t *Bp = B + s * g.sB + b_block(g, b) * g.bB;
     uint32_t *Cp = C + s * g.sC + b * g.bC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
@@ -884,8 +884,8 @@ __global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAG
         if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
         scale = pow2_neg(shift);
     }
-    const uint32_t *Ap = A + s * g.sA + b * g.bA;
-    const uint32_t *Bp = B + s * g.sB + b * g.bB;
+    const uint32_t *Ap = A + s * g.sA + a_block(g, b) * g.bA;
+    const uint32_t *Bp = B + s * g.sB + b_block(g, b) * g.bB;
     uint32_t *Cp = C + s * g.sC + b * g.bC;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1153,8 +1153,8 @@ __global__ void __launch_bounds__(64 * WM * WN)
     int64_t mt, nt;
     tile_coords<4>(t, tiles_m, tiles_n, mt, nt);
     const int64_t m0 = mt * BM, n0 = nt * BN;
-    const float2 *Ap = A + s * g.sA + b * g.bA;
-    const float2 *Bp = B + s * g.sB + b * g.bB;
+    const float2 *Ap = A + s * g.sA + a_block(g, b) * g.bA;
+    const float2 *Bp = B + s * g.sB + b_block(g, b) * g.bB;
     float2 *Cp = C + s * g.sC + b * g.bC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
@@ -1635,6 +1635,28 @@ void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void 
                  const ScaleRefs *sc, hipStream_t st) {
     if (S <= 0) return;
     if (!gemm_supported(kid, dt, al, g_in)) TNC_THROW(TNC_EINVAL, std::string("kernel ") + kernel_name(kid) + " cannot run this shape");
+    {
+        // The batch runs on grid.y, times the column chunks of the VALU
+        // kernels or the split-K parts (at most 64 when it applies); a
+        // batch too large for that (sparse-state steps have one per block)
+        // goes out in several launches.
+        const int64_t fac = std::max<int64_t>(64, (g_in.N + 15) / 16);
+        if (g_in.nb * fac > 65535) {
+            const int64_t chunk = std::max<int64_t>(1, 65535 / fac);
+            const int64_t es = elem_bytes(dt);
+            for (int64_t b0 = 0; b0 < g_in.nb; b0 += chunk) {
+                GemmShape g = g_in;
+                g.nb = std::min(chunk, g_in.nb - b0);
+                const uint8_t *pa = (const uint8_t *)A, *pb = (const uint8_t *)B;
+                if (g.ia) g.ia += b0;
+                else pa += b0 * g.bA * es;
+                if (g.ib) g.ib += b0;
+                else pb += b0 * g.bB * es;
+                launch_gemm(kid, dt, al, pa, pb, (uint8_t *)C + b0 * g.bC * es, g, S, sc, st);
+            }
+            return;
+        }
+    }
     ScaleRefs s = sc ? *sc : ScaleRefs{};
     if (dt != Dtype::C64 && !sc) TNC_THROW(TNC_EINVAL, "16-bit forms need scale bookkeeping");
     s.flag_above = dt == Dtype::F16 ? kF16FlagAbove : 3.0e38f;

@@ -217,22 +217,25 @@ void launch_permute(Dtype dt, const void *src, void *dst, const PermuteDesc &d, 
 //
 // One launch gathers every input tensor of a slice group: block (leaf, slice)
 // copies the sub-tensor of leaf i at the fixed label values of slice
-// sigma = sigma0 + s into the arena, in the order its first step wants, and
+// sigma = sigma0 + s (recomputed labels: the bits above the sliced ones,
+// which a pass adds to the group's base) into the arena, in the order its first step wants, and
 // records its largest component (16-bit forms) and a zero exponent.
 
 template <typename W>
 __global__ void gather_leaves_kernel(const LeafDesc *__restrict__ descs, const int64_t *__restrict__ params,
                                      const W *__restrict__ leafdata, uint8_t *__restrict__ arena,
-                                     uint32_t *__restrict__ maxw, double *__restrict__ expw, int group_base) {
+                                     uint32_t *__restrict__ maxw, double *__restrict__ expw, int64_t group_base,
+                                     const int64_t *__restrict__ spoff) {
     const LeafDesc &L = descs[blockIdx.x];
     const int s = blockIdx.y;
-    if (s >= L.n_slices) return;
+    const int d = blockIdx.z;   // sparse-state block (0 otherwise)
+    if (s >= L.n_slices || d >= L.nd) return;
     const int64_t sigma = params[0] + group_base + s;
-    int64_t so = L.src_off + L.closed_off;
+    int64_t so = L.src_off + L.closed_off + (spoff ? spoff[L.sp_base + d] : 0);
     for (int j = 0; j < L.n_sliced; j++)
         if ((sigma >> L.slice_bit[j]) & 1) so += L.slice_stride[j];
-    W *dp = (W *)(arena + L.dst_byte_off) + (int64_t)s * L.dst_slice_stride;
     const int64_t n = (int64_t)1 << L.rank;
+    W *dp = (W *)(arena + L.dst_byte_off) + (int64_t)s * L.dst_slice_stride + (int64_t)d * n;
     float mx = 0.f;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
         int64_t o = so;
@@ -253,17 +256,18 @@ __global__ void gather_leaves_kernel(const LeafDesc *__restrict__ descs, const i
 
 void launch_gather_leaves_impl(Dtype dt, int n_leaves, const LeafDesc *d_desc, const int64_t *d_params,
                                const void *leafdata, uint8_t *arena, uint32_t *maxw, double *expw,
-                               int group_base, int S, hipStream_t st) {
+                               int64_t group_base, int S, hipStream_t st, const int64_t *spoff, int nd_max) {
     if (n_leaves <= 0) return;
+    const dim3 grid(n_leaves, S, nd_max);
     if (dt == Dtype::C64)
-        hipLaunchKernelGGL((gather_leaves_kernel<uint2>), dim3(n_leaves, S), dim3(64), 0, st, d_desc, d_params,
-                           (const uint2 *)leafdata, arena, (uint32_t *)nullptr, (double *)nullptr, group_base);
+        hipLaunchKernelGGL((gather_leaves_kernel<uint2>), grid, dim3(64), 0, st, d_desc, d_params,
+                           (const uint2 *)leafdata, arena, (uint32_t *)nullptr, (double *)nullptr, group_base, spoff);
     else if (dt == Dtype::F16)
-        hipLaunchKernelGGL((gather_leaves_kernel<HalfWord>), dim3(n_leaves, S), dim3(64), 0, st, d_desc,
-                           d_params, (const HalfWord *)leafdata, arena, maxw, expw, group_base);
+        hipLaunchKernelGGL((gather_leaves_kernel<HalfWord>), grid, dim3(64), 0, st, d_desc, d_params,
+                           (const HalfWord *)leafdata, arena, maxw, expw, group_base, spoff);
     else
-        hipLaunchKernelGGL((gather_leaves_kernel<Bf16Word>), dim3(n_leaves, S), dim3(64), 0, st, d_desc,
-                           d_params, (const Bf16Word *)leafdata, arena, maxw, expw, group_base);
+        hipLaunchKernelGGL((gather_leaves_kernel<Bf16Word>), grid, dim3(64), 0, st, d_desc, d_params,
+                           (const Bf16Word *)leafdata, arena, maxw, expw, group_base, spoff);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -276,12 +280,16 @@ template <typename W>
 __global__ void accumulate_kernel(const W *__restrict__ R, int rank, int S, int64_t ss,
                                   const double *__restrict__ expR, int es, int64_t nbits,
                                   const uint64_t *__restrict__ bits, const int *__restrict__ qob,
-                                  double *__restrict__ acc) {
+                                  double *__restrict__ acc, const int32_t *__restrict__ map) {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= nbits) return;
-    uint64_t x = bits[j];
     int64_t idx = 0;
-    for (int b = 0; b < rank; b++) idx |= (int64_t)((x >> qob[b]) & 1ull) << b;
+    if (map) {
+        idx = map[j];   // sparse state: the root block of bitstring j
+    } else {
+        const uint64_t x = bits[j];
+        for (int b = 0; b < rank; b++) idx |= (int64_t)((x >> qob[b]) & 1ull) << b;
+    }
     double re = acc[2 * j], im = acc[2 * j + 1];
     for (int s = 0; s < S; s++) {
         double2 v = word_to_double2(R[s * ss + idx]);
@@ -294,18 +302,19 @@ __global__ void accumulate_kernel(const W *__restrict__ R, int rank, int S, int6
 }
 
 void launch_accumulate(Dtype dt, const void *R, int rank, int S, int64_t ss, const double *expR, int es,
-                       int64_t nbits, const uint64_t *d_bits, const int *d_qob, double *acc, hipStream_t st) {
+                       int64_t nbits, const uint64_t *d_bits, const int *d_qob, double *acc, hipStream_t st,
+                       const int32_t *d_map) {
     if (nbits <= 0 || S <= 0) return;
     int g = (int)((nbits + 255) / 256);
     if (dt == Dtype::C64)
         hipLaunchKernelGGL((accumulate_kernel<uint2>), dim3(g), dim3(256), 0, st, (const uint2 *)R, rank, S, ss,
-                           (const double *)nullptr, es, nbits, d_bits, d_qob, acc);
+                           (const double *)nullptr, es, nbits, d_bits, d_qob, acc, d_map);
     else if (dt == Dtype::F16)
         hipLaunchKernelGGL((accumulate_kernel<HalfWord>), dim3(g), dim3(256), 0, st, (const HalfWord *)R, rank, S,
-                           ss, expR, es, nbits, d_bits, d_qob, acc);
+                           ss, expR, es, nbits, d_bits, d_qob, acc, d_map);
     else
         hipLaunchKernelGGL((accumulate_kernel<Bf16Word>), dim3(g), dim3(256), 0, st, (const Bf16Word *)R, rank, S,
-                           ss, expR, es, nbits, d_bits, d_qob, acc);
+                           ss, expR, es, nbits, d_bits, d_qob, acc, d_map);
     HIP_CHECK(hipGetLastError());
 }
 

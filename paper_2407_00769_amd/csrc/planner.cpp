@@ -167,7 +167,8 @@ int choose_kernel(Dtype dt, Algo al, const GemmShape &g) {
 }
 
 Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_sliced, const int32_t *sliced,
-                 int n_open, const int32_t *open_q, tnc_precision prec) {
+                 int n_open, const int32_t *open_q, tnc_precision prec, int n_recompute, const int32_t *recompute,
+                 int64_t n_sparse, const uint64_t *sparse_bits) {
     Analysis an;
     an.dt = dtype_of(prec);
     an.al = algo_of(prec);
@@ -177,6 +178,9 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
     const int L = net.n_labels;
     if (n_steps != nT - 1) TNC_THROW(TNC_EINVAL, "path must have n_tensors - 1 steps");
     if (n_sliced < 0 || n_sliced > 62) TNC_THROW(TNC_EINVAL, "n_sliced out of range");
+    if (n_recompute < 0 || n_recompute > 8 || n_sliced + n_recompute > 62)
+        TNC_THROW(TNC_EINVAL, "n_recompute out of [0, 8] (or sliced + recomputed labels above 62)");
+    if (n_recompute > 0 && !recompute) TNC_THROW(TNC_EINVAL, "recompute labels are NULL");
     if (n_open < 0 || n_open > net.n_qubits) TNC_THROW(TNC_EINVAL, "n_open out of range");
 
     an.fixed.assign(L, -1);
@@ -194,6 +198,12 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
     }
     for (int q = 0; q < net.n_qubits; q++)
         if (!open[q]) an.fixed[net.output_labels[q]] = 1;
+    an.sparse = sparse_bits != nullptr;
+    if (an.sparse) {
+        if (n_open != 0) TNC_THROW(TNC_EINVAL, "a sparse-state plan takes no open qubits: every qubit follows the bitstrings");
+        if (n_sparse < 1) TNC_THROW(TNC_EINVAL, "a sparse-state plan needs at least one bitstring");
+        if (net.hyperedges) TNC_THROW(TNC_EUNSUPPORTED, "sparse-state plans take networks whose labels join two tensors");
+    }
     for (int j = 0; j < n_sliced; j++) {
         int l = sliced[j];
         if (l < 0 || l >= L) TNC_THROW(TNC_EINVAL, "sliced label " + lbl(l) + " not in the network");
@@ -203,6 +213,19 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         an.slice_bit[l] = j;
     }
     an.n_sliced = n_sliced;
+    // recomputed labels: fixed per pass; a pass's values are the slice id
+    // bits above the sliced ones
+    std::vector<char> is_rec(L, 0);
+    for (int j = 0; j < n_recompute; j++) {
+        int l = recompute[j];
+        if (l < 0 || l >= L) TNC_THROW(TNC_EINVAL, "recomputed label " + lbl(l) + " not in the network");
+        if (is_output[l] >= 0) TNC_THROW(TNC_EINVAL, "recomputed label " + lbl(l) + " is an output label");
+        if (an.fixed[l] == 0) TNC_THROW(TNC_EINVAL, "recomputed label " + lbl(l) + " is sliced or listed twice");
+        an.fixed[l] = 0;
+        an.slice_bit[l] = n_sliced + j;
+        is_rec[l] = 1;
+    }
+    an.n_recompute = n_recompute;
 
     // input tensors with the fixed labels removed
     std::vector<int> needed(L, 0);
@@ -213,6 +236,8 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         for (int l : net.labels[i]) {
             if (an.fixed[l] >= 0) {
                 if (an.fixed[l] == 0) t.dep = true;
+                if (is_rec[l]) t.inner = true;
+                if (an.sparse && is_output[l] >= 0) t.sp_mask |= 1ull << is_output[l];
                 continue;
             }
             t.labels.push_back(l);
@@ -246,7 +271,10 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         Y.consumer = s;
         Z.producer = s;
         Z.dep = X.dep || Y.dep;
+        Z.inner = X.inner || Y.inner;
+        Z.sp_mask = X.sp_mask | Y.sp_mask;
         st.dep = Z.dep;
+        st.inner = Z.inner;
         std::vector<char> inx(L, 0), iny(L, 0);
         for (int l : X.labels) inx[l] = 1;
         for (int l : Y.labels) iny[l] = 1;
@@ -288,6 +316,55 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             cnt++;
         }
         if (cnt != n_open) TNC_THROW(TNC_EINVAL, "an open output label never reaches the root");
+    }
+
+    if (an.sparse) {
+        // blocks of every tensor: the distinct values of the requested
+        // bitstrings on its qubits (sorted), and for each step which operand
+        // block every result block reads
+        const size_t nT2 = an.tensors.size();
+        std::vector<std::vector<uint64_t>> keys(nT2);
+        auto keys_of = [&](uint64_t m) {
+            std::vector<uint64_t> k(sparse_bits, sparse_bits + n_sparse);
+            for (auto &v : k) v &= m;
+            std::sort(k.begin(), k.end());
+            k.erase(std::unique(k.begin(), k.end()), k.end());
+            return k;
+        };
+        for (int i = 0; i < nT; i++) {
+            keys[i] = keys_of(an.tensors[i].sp_mask);
+            an.tensors[i].nd = (int64_t)keys[i].size();
+        }
+        an.leaf_keys.assign(keys.begin(), keys.begin() + nT);
+        for (int s = 0; s < n_steps; s++) {
+            StepRec &st = an.steps[s];
+            TensorRec &Z = an.tensors[st.z];
+            keys[st.z] = keys_of(Z.sp_mask);
+            Z.nd = (int64_t)keys[st.z].size();
+            if (Z.nd > (int64_t)1 << 31) TNC_THROW(TNC_EUNSUPPORTED, "more than 2^31 sparse blocks");
+            auto side = [&](int x, int &mode, std::vector<int32_t> &idx) {
+                const TensorRec &X = an.tensors[x];
+                if (X.sp_mask == Z.sp_mask) mode = 0;
+                else if (X.sp_mask == 0) mode = 1;
+                else {
+                    mode = 2;
+                    idx.resize(Z.nd);
+                    for (int64_t d = 0; d < Z.nd; d++) {
+                        const uint64_t v = keys[st.z][d] & X.sp_mask;
+                        idx[d] = (int32_t)(std::lower_bound(keys[x].begin(), keys[x].end(), v) - keys[x].begin());
+                    }
+                }
+            };
+            side(st.a, st.a_mode, st.a_idx);
+            side(st.b, st.b_mode, st.b_idx);
+            if (st.x >= nT) std::vector<uint64_t>().swap(keys[st.x]);
+            if (st.y >= nT) std::vector<uint64_t>().swap(keys[st.y]);
+        }
+        const auto &rk = keys[an.root];
+        const uint64_t rm = an.tensors[an.root].sp_mask;
+        an.root_map.resize(n_sparse);
+        for (int64_t i = 0; i < n_sparse; i++)
+            an.root_map[i] = (int32_t)(std::lower_bound(rk.begin(), rk.end(), sparse_bits[i] & rm) - rk.begin());
     }
 
     // step at which each label is summed (open outputs: never)
@@ -503,13 +580,15 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             int low = Z.labels.empty() ? -1 : Z.labels.back();
             st.c_nc = (low >= 0 && std::find(m_o.begin(), m_o.end(), low) != m_o.end()) ? 0 : 1;
         }
-        st.nb = (int64_t)1 << st.beta.size();
+        // sparse state: the batch is the result's blocks (no batch labels there)
+        st.nb = an.sparse ? Z.nd : (int64_t)1 << st.beta.size();
         st.M = (int64_t)1 << st.m.size();
         st.N = (int64_t)1 << st.n.size();
         st.K = (int64_t)1 << st.k.size();
         st.flops = 8.0 * (double)st.nb * (double)st.M * (double)st.N * (double)st.K;
-        st.bytes = es * (std::ldexp(1.0, A.rank()) + std::ldexp(1.0, B.rank()) + std::ldexp(1.0, Z.rank()));
-        st.perm_bytes = (st.perm_a ? 2.0 * es * szA : 0.0) + (st.perm_b ? 2.0 * es * szB : 0.0);
+        st.bytes = es * ((double)A.nd * std::ldexp(1.0, A.rank()) + (double)B.nd * std::ldexp(1.0, B.rank()) +
+                         (double)Z.nd * std::ldexp(1.0, Z.rank()));
+        st.perm_bytes = (st.perm_a ? 2.0 * es * (double)A.nd * szA : 0.0) + (st.perm_b ? 2.0 * es * (double)B.nd * szB : 0.0);
         st.hoist_a = st.perm_a && st.dep && !A.dep;
         st.hoist_b = st.perm_b && st.dep && !B.dep;
         if (!derive_seg(A.labels, st.m, st.am) || !derive_seg(A.labels, st.k, st.ak) ||
@@ -576,13 +655,14 @@ int64_t plan_memory(Analysis &an, int S, bool assign) {
     const int es = elem_bytes(an.dt);
     Arena ar;
     auto bytes_of = [&](const TensorRec &t) {
-        return (int64_t)es * ((int64_t)1 << t.rank()) * (t.dep ? S : 1);
+        return (int64_t)es * ((int64_t)1 << t.rank()) * t.nd * (t.dep ? S : 1);
     };
     std::vector<int64_t> off(an.tensors.size(), -1);
     const int nT = (int)(an.tensors.size() + 1) / 2;
+    auto cls_t = [&](int t) { return exec_class(an.tensors[t].dep, an.tensors[t].inner); };
     // invariant phase
     for (int i = 0; i < nT; i++)
-        if (!an.tensors[i].dep) off[i] = ar.alloc(bytes_of(an.tensors[i]));
+        if (cls_t(i) == 0) off[i] = ar.alloc(bytes_of(an.tensors[i]));
     std::vector<int64_t> scr_a(an.steps.size(), -1), scr_b(an.steps.size(), -1);
     auto run_step = [&](int s) {
         StepRec &st = an.steps[s];
@@ -595,8 +675,10 @@ int64_t plan_memory(Analysis &an, int S, bool assign) {
         if (pb) ar.release(scr_b[s], bytes_of(B));
         for (int t : {st.a, st.b}) {
             const TensorRec &T = an.tensors[t];
-            // an invariant operand of a dependent step is read by every group: kept
-            if (T.dep == st.dep) ar.release(off[t], bytes_of(T));
+            // an operand of an earlier class (invariant for a slice step,
+            // prefix for a recomputed one) is read again by every group or
+            // pass: kept
+            if (cls_t(t) == exec_class(st.dep, st.inner)) ar.release(off[t], bytes_of(T));
         }
     };
     for (int s = 0; s < (int)an.steps.size(); s++)
@@ -613,11 +695,13 @@ int64_t plan_memory(Analysis &an, int S, bool assign) {
             ar.release(off[st.b], bytes_of(an.tensors[st.b]));
         }
     }
-    // dependent phase (one slice group)
-    for (int i = 0; i < nT; i++)
-        if (an.tensors[i].dep) off[i] = ar.alloc(bytes_of(an.tensors[i]));
-    for (int s = 0; s < (int)an.steps.size(); s++)
-        if (an.steps[s].dep) run_step(s);
+    // dependent phase (one slice group): the prefix, then one recomputation pass
+    for (int c = 1; c <= 2; c++) {
+        for (int i = 0; i < nT; i++)
+            if (cls_t(i) == c) off[i] = ar.alloc(bytes_of(an.tensors[i]));
+        for (int s = 0; s < (int)an.steps.size(); s++)
+            if (exec_class(an.steps[s].dep, an.steps[s].inner) == c) run_step(s);
+    }
     if (assign) {
         for (size_t i = 0; i < an.tensors.size(); i++) an.tensors[i].off = off[i];
         for (size_t s = 0; s < an.steps.size(); s++) {
@@ -635,14 +719,17 @@ void fill_stats(const Analysis &an, tnc_plan_stats &st) {
     st.max_rank = an.max_rank;
     st.out_rank = an.tensors[an.root].rank();
     double pe = 0;
-    for (auto &t : an.tensors) pe = std::max(pe, std::ldexp(1.0, t.rank()));
+    for (auto &t : an.tensors) pe = std::max(pe, (double)t.nd * std::ldexp(1.0, t.rank()));
     st.peak_elems_per_slice = pe;
+    const double passes = std::ldexp(1.0, an.n_recompute);
+    st.n_recompute = an.n_recompute;
     for (auto &s : an.steps) {
         if (s.dep) {
+            const double w = s.inner ? passes : 1.0;
             st.n_dep_steps++;
-            st.flops_per_slice += s.flops;
-            st.bytes_per_slice += s.bytes + s.perm_bytes;
-            st.permute_bytes_per_slice += s.perm_bytes;
+            st.flops_per_slice += w * s.flops;
+            st.bytes_per_slice += w * (s.bytes + s.perm_bytes);
+            st.permute_bytes_per_slice += w * s.perm_bytes;
         } else {
             st.flops_invariant += s.flops;
         }

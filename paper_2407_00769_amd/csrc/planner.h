@@ -13,6 +13,12 @@ namespace tnc {
 struct TensorRec {
     std::vector<int> labels;    // storage order, first = slowest
     bool dep = false;           // depends on the slice id
+    bool inner = false;         // holds a recomputed label in its sub-tree (computed once per pass)
+    // sparse state: the qubits whose output labels this tensor holds, and the
+    // number of their distinct value combinations among the requested
+    // bitstrings; the tensor is stored as nd dense blocks [d][labels]
+    uint64_t sp_mask = 0;
+    int64_t nd = 1;
     bool leaf = false;
     int producer = -1;          // step index, or -1 for an input tensor
     int consumer = -1;          // step index, or -1 for the root
@@ -32,6 +38,11 @@ struct StepRec {
     Seg am, ak, bn, bk, cm, cn;        // where each GEMM index lives in A, B and the result
     bool hoist_a = false, hoist_b = false;   // permute of an invariant operand, done once per call
     bool dep = false;
+    bool inner = false;               // runs once per recomputation pass
+    // sparse state: which dense block of A and B each result block d reads:
+    // mode 0 the same d, 1 block 0 for every d, 2 the index array
+    int a_mode = 0, b_mode = 0;
+    std::vector<int32_t> a_idx, b_idx;
     int kernel = K_NAIVE;
     double flops = 0;                 // per slice (or once, if invariant)
     double bytes = 0;                 // GEMM bytes per slice
@@ -45,15 +56,37 @@ struct Analysis {
     std::vector<int> slice_bit;       // per label: bit of the slice id (sliced labels)
     std::vector<int> open_qubit_of_label;
     int root = -1;
-    int n_sliced = 0;
+    int n_sliced = 0;                 // sliced labels (slice ids 0 .. 2^n_sliced - 1)
+    int n_recompute = 0;              // recomputed labels: 2^n_recompute passes per slice
+    // sparse state (uncorrelated bitstrings): every output label is replaced
+    // by a block index over the distinct values of the tensor's qubits
+    bool sparse = false;
+    std::vector<std::vector<uint64_t>> leaf_keys;   // per input tensor: its blocks' qubit values
+    std::vector<int32_t> root_map;                  // per requested bitstring: its block of the root
     int max_rank = 0;
     Dtype dt = Dtype::C64;
     Algo al = Algo::M4;
 };
 
-// Validate and analyse; throws tnc::Error.
+// Validate and analyse; throws tnc::Error.  Recomputed labels (paper Sec.
+// 3.4.1) are fixed like sliced ones, but per pass: their values are the slice
+// id bits n_sliced + j of a pass, and the steps whose sub-tree holds one of
+// them (the suffix) run once per pass while the rest (the prefix) run once
+// per slice.
+//
+// Sparse state (paper Sec. 3.4.2): with `sparse_bits`, the amplitudes of
+// those n_sparse bitstrings are computed together whatever bits they share.
+// Every output label leaves the dense labels; a tensor holding the output
+// labels of qubit set Q is stored as one dense block per distinct value of
+// the bitstrings restricted to Q, and a step forms each result block from the
+// operand blocks with the matching values (a gathered multi-pair GEMM).
 Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_sliced, const int32_t *sliced,
-                 int n_open, const int32_t *open_q, tnc_precision prec);
+                 int n_open, const int32_t *open_q, tnc_precision prec, int n_recompute = 0,
+                 const int32_t *recompute = nullptr, int64_t n_sparse = 0, const uint64_t *sparse_bits = nullptr);
+
+// Execution class of a tensor or step: 0 slice-invariant (once per call),
+// 1 slice prefix (once per slice group), 2 recomputed suffix (once per pass).
+inline int exec_class(bool dep, bool inner) { return !dep ? 0 : (inner ? 2 : 1); }
 
 // Byte offsets of every tensor and scratch buffer for S slices in flight;
 // returns the arena peak in bytes.
@@ -89,6 +122,7 @@ struct Simplified {
 // rank cap of host steps: TNC_HOST_RANK if set (0 switches the pass off), else kDefaultHostRank
 int host_rank_cap();
 Simplified presimplify(const Network &net, int n_steps, const int32_t *ssa, int n_sliced, const int32_t *sliced,
-                       int n_open, const int32_t *open_q, int max_rank);
+                       int n_open, const int32_t *open_q, int max_rank, int n_recompute = 0,
+                       const int32_t *recompute = nullptr);
 
 }  // namespace tnc

@@ -10,8 +10,8 @@
 // always rounds the same way in FP16).  The contraction tree is the given one;
 // only where its leaf-level steps run changes.
 //
-// Labels that the plan fixes (sliced labels, output labels of closed qubits)
-// are never summed here: a merged tensor keeps them, and the slice gather
+// Labels that the plan fixes (sliced and recomputed labels, output labels of
+// closed qubits) are never summed here: a merged tensor keeps them, and the slice gather
 // selects their values per slice and per call as for any input tensor.  A
 // label that both operands hold and no other tensor needs is summed (paper
 // Eq. contraction); a label still held elsewhere stays, as a batch label.
@@ -80,7 +80,7 @@ int host_rank_cap() {
 }
 
 Simplified presimplify(const Network &net, int n_steps, const int32_t *ssa, int n_sliced, const int32_t *sliced,
-                       int n_open, const int32_t *open_q, int max_rank) {
+                       int n_open, const int32_t *open_q, int max_rank, int n_recompute, const int32_t *recompute) {
     const int nT = net.n_tensors;
     const int L = net.n_labels;
     if (n_steps != nT - 1) TNC_THROW(TNC_EINVAL, "path must have n_tensors - 1 steps");
@@ -104,6 +104,8 @@ Simplified presimplify(const Network &net, int n_steps, const int32_t *ssa, int 
     }
     for (int j = 0; j < n_sliced; j++)
         if (sliced[j] >= 0 && sliced[j] < L) fixed[sliced[j]] = 1;
+    for (int j = 0; j < n_recompute; j++)
+        if (recompute[j] >= 0 && recompute[j] < L) fixed[recompute[j]] = 1;
     // holders of each label among the live tensors
     std::vector<int> holders(L, 0);
     for (const auto &ls : net.labels)

@@ -230,3 +230,24 @@ def test_stored_53_qubit_path_layouts_keep_permutes_low():
     assert info["permute_bytes_per_slice"] <= 1.0e11, info["permute_bytes_per_slice"]
     assert 2.3e14 < info["flops_per_slice"] < 2.6e14
     T.tnc_network_destroy(net)
+
+
+def test_recompute_path_meets_the_cap_and_rejects_bad_labels():
+    """Recomputation (Sec. 3.4.1): the chosen labels bring one pass under the
+    cap, the prefix is shared (no more work than slicing them as well), and
+    invalid labels are refused."""
+    c, st, net, n = _net(0)
+    open_q = list(range(6, 12))
+    ssa, sl, _ = T.tnc_search(net, n, open_q, 9, restarts=2, seed=1)
+    base = T.tnc_plan_analyze(net, ssa, sl, open_q, "c64")
+    cap = base["max_rank"] - 1
+    rec = T.tnc_recompute_path(net, ssa, sl, open_q, cap)
+    assert len(rec) >= 1 and not set(rec) & set(sl)
+    r = T.tnc_plan_analyze(net, ssa, sl, open_q, "c64", recompute=rec)
+    s = T.tnc_plan_analyze(net, ssa, np.concatenate([sl, rec]), open_q, "c64")
+    assert r["max_rank"] <= cap and r["n_recompute"] == len(rec)
+    assert r["peak_bytes"] < base["peak_bytes"]
+    assert r["flops_per_slice"] <= s["flops_per_slice"] * 2 ** len(rec) * (1 + 1e-12)
+    for bad in ([st.output_labels[0]], [int(sl[0])] if len(sl) else [st.output_labels[1]], [int(rec[0]), int(rec[0])]):
+        with pytest.raises(T.TncError):
+            T.tnc_plan_analyze(net, ssa, sl, open_q, "c64", recompute=bad)
