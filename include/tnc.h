@@ -398,6 +398,24 @@ int tnc_quant_sizes(int32_t kind, int64_t n, int32_t group, int64_t *code_bytes,
  * (host, may be NULL) receives the device time of the kernels. */
 int tnc_quantize(tnc_ctx *ctx, int32_t kind, int64_t n, const float *x, int32_t group, void *codes,
                  float *scales, float *zeros, double *ms_out);
+/* tnc_quantize for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid device allocation.  It
+ * needs no context and makes no allocation of any kind (no hipMalloc, no
+ * events): the min/max partials of the half and int8 kinds go to a
+ * file-scope device array of 512 float2 (4 KB) that each GPU the library runs
+ * on holds until the process ends; int4 uses none.  The array's address on a
+ * device is looked up (hipGetSymbolAddress) on the first call made with that
+ * device current.  Arguments as for tnc_quantize; the work is enqueued on
+ * hip_stream (a hipStream_t, NULL = the null stream) of the current device,
+ * and the call returns without waiting for it.  Results are bit-identical to
+ * tnc_quantize's.  Every call on a GPU shares that GPU's array and every
+ * partial is written before it is read, so nothing needs clearing; calls whose
+ * work overlaps on one GPU (different streams, no ordering) race on it and
+ * must be serialized by the caller.  TNC_EINVAL on a bad kind, group, length,
+ * NULL or misaligned buffer; no length exceeds the array (the min/max pass
+ * uses at most 512 blocks for any n). */
+int tnc_quantize_noalloc(int32_t kind, int64_t n, const float *x, int32_t group, void *codes, float *scales,
+                         float *zeros, void *hip_stream);
 /* Decode n values from codes, scales and zeros (device) into x (device,
  * 16-byte aligned, float32).  Same stream and timing behaviour. */
 int tnc_dequantize(tnc_ctx *ctx, int32_t kind, int64_t n, const void *codes, const float *scales,

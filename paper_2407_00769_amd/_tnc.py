@@ -104,6 +104,7 @@ _SIGS = {
     "tnc_quant_sizes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "tnc_quantize": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_int32, vp, vp, vp, c_double_p]),
+    "tnc_quantize_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_int32, vp, vp, vp, vp]),
     "tnc_dequantize": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, ctypes.c_int32, vp,
                                       c_double_p]),
     "tnc_plan_set_codec": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -485,6 +486,16 @@ def tnc_quantize(ctx, kind, x, group=0):
     _check(lib.tnc_quantize(ctx, k, n, _dptr(x), int(group), _dptr(codes), _dptr(scales), _dptr(zeros),
                             ctypes.byref(ms)))
     return codes[:cb], scales[:ng], zeros[:ng], ms.value
+
+
+def tnc_quantize_noalloc(kind, x, codes, scales, zeros, group=0, stream=None):
+    """The allocation-free quantize: x, codes, scales, zeros are caller-owned
+    device tensors (sizes from tnc_quant_sizes); the work is enqueued on
+    `stream` (a torch stream, None = the null stream) without waiting."""
+    k = QKINDS.get(kind, kind)
+    sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib.tnc_quantize_noalloc(k, x.numel(), _dptr(x), int(group), _dptr(codes), _dptr(scales), _dptr(zeros),
+                                    sp))
 
 
 def tnc_dequantize(ctx, kind, n, codes, scales, zeros, group=0):

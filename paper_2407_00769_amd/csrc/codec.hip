@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <cstdint>
+#include <mutex>
 
 #include "common.h"
 
@@ -401,3 +403,58 @@ void launch_dequantize(int kind, int64_t n, int group, const void *codes, const 
 }
 
 }  // namespace tnc
+
+// ------------------------------------------------------------------ quantize without allocation
+namespace tnc {
+
+// The min/max partials of the whole-tensor kinds live in this array for
+// tnc_quantize_noalloc: one copy per GPU, held until the process ends.  Host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// each device (the array's name is a host-side stand-in there).
+static __device__ __align__(256) float2 scratch[kQuantPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float2 *g_scratch[kMaxDevices] = {};
+
+// the array's device address on the current device, resolved once per device
+float2 *scratch_on_current_device() {
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) TNC_THROW(TNC_EUNSUPPORTED, "device id above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) TNC_THROW(TNC_EDEVICE, "hipGetSymbolAddress returned NULL for the codec scratch array");
+        g_scratch[dev] = (float2 *)p;
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
+}  // namespace tnc
+
+extern "C" int tnc_quantize_noalloc(int32_t kind, int64_t n, const float *x, int32_t group, void *codes,
+                                    float *scales, float *zeros, void *hip_stream) {
+    using namespace tnc;
+    try {
+        if (n < 0) TNC_THROW(TNC_EINVAL, "negative length");
+        const int g = codec_group(kind, group);
+        if (n == 0) return TNC_OK;
+        if (!x || !codes || !scales || !zeros) TNC_THROW(TNC_EINVAL, "NULL buffer");
+        if (((uintptr_t)x & 15u) || ((uintptr_t)codes & 15u))
+            TNC_THROW(TNC_EINVAL, "values and codes must be 16-byte aligned");
+        // the whole-tensor kinds write one partial per block of the min/max
+        // pass; that pass never launches more blocks than the array holds
+        if ((kind == 0 || kind == 1) && grid_cap(n, 256 * 64, kQuantPartials) > kQuantPartials)
+            TNC_THROW(TNC_EINVAL, "min/max pass needs more partials than the scratch array holds");
+        float2 *part = scratch_on_current_device();
+        launch_quantize(kind, n, g, x, codes, scales, zeros, part, (hipStream_t)hip_stream);
+        return TNC_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    }
+}
