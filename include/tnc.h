@@ -92,6 +92,7 @@ typedef struct {
                                    /* FP64 before the device path (not in n_steps)          */
     int32_t n_recompute;           /* recomputed labels (2^n_recompute passes per slice);   */
                                    /* flops and bytes per slice count every pass            */
+    int32_t n_padded_steps;        /* sparse-state steps on the padded-index scheme         */
 } tnc_plan_stats;
 
 /* Results of one tnc_execute. */
@@ -205,10 +206,15 @@ int tnc_plan_create_recompute(tnc_ctx *ctx, const tnc_network *net, int32_t n_st
  * closed or left open: a tensor holding the output labels of qubit set Q is
  * stored as one dense block per distinct value the bitstrings take on Q, and
  * each step forms every result block from the operand blocks with the
- * matching values -- a batched GEMM whose operands are gathered through index
- * arrays (the multi-pair contraction of the figure, its first indexing
- * scheme; the index is read inside the GEMM, so no gathered copy of an
- * operand is made and no chunking is needed).  tnc_execute then takes exactly
+ * matching values (the multi-pair contraction of the figure), by one of its
+ * two indexing schemes, chosen per step by the bytes it moves: (1) a batched
+ * GEMM that reads its operand blocks through index arrays (no gathered copy
+ * is made); (2) when many result blocks share an A block, the padded
+ * two-dimensional index: each A block is multiplied once by B_P, the B
+ * blocks of its result blocks side by side (index -1: zero blocks), and the
+ * result blocks are taken out of that product; B_P and the product are built
+ * a chunk of A blocks at a time in the arena, so they stay within the larger
+ * of the result's size and 2^24 entries.  tnc_execute then takes exactly
  * these bitstrings (TNC_EINVAL otherwise) and returns their amplitudes summed
  * over the slice range.  Sliced labels as for tnc_plan_create.  Networks with
  * hyperedges: TNC_EUNSUPPORTED.  The arena holds every tensor's blocks, so

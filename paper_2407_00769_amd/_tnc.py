@@ -53,7 +53,7 @@ class tnc_plan_stats(ctypes.Structure):
                 ("bytes_per_slice", ctypes.c_double), ("permute_bytes_per_slice", ctypes.c_double),
                 ("peak_bytes", ctypes.c_double), ("peak_elems_per_slice", ctypes.c_double),
                 ("tune_seconds", ctypes.c_double), ("n_host_steps", ctypes.c_int32),
-                ("n_recompute", ctypes.c_int32)]
+                ("n_recompute", ctypes.c_int32), ("n_padded_steps", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -180,6 +180,11 @@ int64_t splitk_bytes(int kid, Dtype dt, Algo al, const GemmShape &g, int S);
 void launch_gemm(int kid, Dtype dt, Algo al, const void *A, const void *B, void *C,
                  const GemmShape &g, int S, const ScaleRefs *sc, hipStream_t st);
 void launch_convert_c128(const double *src, int64_t n, Dtype dt, void *dst, hipStream_t st);
+// Sparse state: destination block j (of `block` entries, per slice) takes
+// source block idx[j] - lo when that lies in [0, hi - lo), else is zeroed
+// (fill) or left as it is.
+void launch_block_copy(Dtype dt, const void *src, int64_t src_ss, void *dst, int64_t dst_ss, const int32_t *idx,
+                       int64_t n_blocks, int64_t lo, int64_t hi, int64_t block, int S, bool fill, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
 void launch_fill_random(Dtype dt, void *p, int64_t n_words, uint32_t seed, hipStream_t st);

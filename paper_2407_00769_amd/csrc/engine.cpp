@@ -298,8 +298,16 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
         std::vector<int32_t> idx;
         p->a_idx_off.assign(an.steps.size(), -1);
         p->b_idx_off.assign(an.steps.size(), -1);
+        p->bp_idx_off.assign(an.steps.size(), -1);
+        p->cp_idx_off.assign(an.steps.size(), -1);
         for (size_t k = 0; k < an.steps.size(); k++) {
             const StepRec &rec = an.steps[k];
+            if (rec.scheme == 2) {
+                p->bp_idx_off[k] = (int64_t)idx.size();
+                idx.insert(idx.end(), rec.bp_idx.begin(), rec.bp_idx.end());
+                p->cp_idx_off[k] = (int64_t)idx.size();
+                idx.insert(idx.end(), rec.cp_idx.begin(), rec.cp_idx.end());
+            }
             if (rec.a_mode == 2) {
                 p->a_idx_off[k] = (int64_t)idx.size();
                 idx.insert(idx.end(), rec.a_idx.begin(), rec.a_idx.end());
@@ -349,7 +357,7 @@ static void build_plan(tnc_plan *p, const Network &net, int max_sif) {
     int64_t part_bytes = 0;
     for (const auto &rec : an.steps) {
         const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
-        GemmShape g = step_gemm(rec);
+        GemmShape g = step_gemm_exec(rec);
         g.sA = A.dep ? 1 : 0;
         g.sB = B.dep ? 1 : 0;
         g.sC = 1;
@@ -375,13 +383,19 @@ static GemmShape plan_step_shape(const tnc_plan *p, int s) {
     const StepRec &rec = an.steps[s];
     const TensorRec &A = an.tensors[rec.a], &B = an.tensors[rec.b], &Z = an.tensors[rec.z];
     const int64_t na = (int64_t)1 << A.rank(), nbb = (int64_t)1 << B.rank(), nz = (int64_t)1 << Z.rank();
-    GemmShape g = step_gemm(rec);
+    GemmShape g = step_gemm_exec(rec);
     g.sA = A.dep ? na * A.nd : 0;
     g.sB = B.dep ? nbb * B.nd : 0;
     g.sC = nz * Z.nd;
     g.part = p->d_part;
     g.part_cap = p->part_bytes;
     g.split_slices = rec.dep ? p->S : 1;   // the slice count d_part was sized for
+    if (rec.scheme == 2) {
+        // one chunk of A blocks against its B_P and C_P scratch (slice-major)
+        g.sB = rec.chunk * rec.mr * nbb;
+        g.sC = rec.chunk * rec.mr * nz;
+        return g;
+    }
     if (an.sparse) {
         if (rec.a_mode == 1) g.bA = 0;
         if (rec.b_mode == 1) g.bB = 0;
@@ -535,10 +549,15 @@ double autotune_plan(tnc_plan *p) {
         const void *pa = ws + (rec.perm_a ? rec.scr_a : A.off);
         const void *pb = ws + (rec.perm_b ? rec.scr_b : B.off);
         void *pc = ws + Z.off;
+        if (rec.scheme == 2) {   // the per-chunk GEMM reads B_P and writes C_P
+            pb = ws + rec.scr_bp;
+            pc = ws + rec.scr_cp;
+        }
         {
             // the arena holds no data yet: give the operands random values
             const int64_t wa = (A.dep ? Sl : 1) * A.nd * na * elem_bytes(dt) / 4,
-                          wb = (B.dep ? Sl : 1) * B.nd * nbb * elem_bytes(dt) / 4;
+                          wb = rec.scheme == 2 ? (int64_t)Sl * rec.chunk * rec.mr * nbb * elem_bytes(dt) / 4
+                                               : (B.dep ? Sl : 1) * B.nd * nbb * elem_bytes(dt) / 4;
             launch_fill_random(dt, (void *)pa, wa, 0x5eed0000u + (uint32_t)rec.a, st);
             launch_fill_random(dt, (void *)pb, wb, 0x5eed8000u + (uint32_t)rec.b, st);
         }
@@ -830,7 +849,24 @@ void enqueue_step(tnc_plan *p, int s, int S_g, hipStream_t st, StepTimer *tm = n
         sc.flag = p->d_flags + s;
     }
     if (tm) HIP_CHECK(hipEventRecord(tm->e[1], st));
-    launch_gemm(rec.kernel, dt, an.al, pa, pb, ws + Z.off, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+    if (rec.scheme == 2) {
+        // second sparse-state scheme, a chunk of A blocks at a time: B_P from
+        // B's blocks (index -1: zeros), the GEMM into C_P, C's blocks out of C_P
+        const int64_t nbb = (int64_t)1 << B.rank(), na = (int64_t)1 << A.rank();
+        for (int64_t a0 = 0; a0 < A.nd; a0 += rec.chunk) {
+            const int64_t nbc = std::min<int64_t>(rec.chunk, A.nd - a0);
+            launch_block_copy(dt, pb, B.dep ? nbb * B.nd : 0, ws + rec.scr_bp, g.sB, p->d_idx + p->bp_idx_off[s] + a0 * rec.mr,
+                              nbc * rec.mr, 0, B.nd, nbb, Sl, true, st);
+            GemmShape gc = g;
+            gc.nb = nbc;
+            launch_gemm(rec.kernel, dt, an.al, (const uint8_t *)pa + a0 * na * es, ws + rec.scr_bp, ws + rec.scr_cp, gc,
+                        Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+            launch_block_copy(dt, ws + rec.scr_cp, g.sC, ws + Z.off, nz * Z.nd, p->d_idx + p->cp_idx_off[s], Z.nd,
+                              a0 * rec.mr, (a0 + nbc) * rec.mr, nz, Sl, false, st);
+        }
+    } else {
+        launch_gemm(rec.kernel, dt, an.al, pa, pb, ws + Z.off, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+    }
     if (s == p->codec_step) {
         // the result of this step passes through the exchange codec, one
         // slice at a time, as if it were sent to another device

@@ -79,7 +79,7 @@ struct tnc_plan {
     int64_t *d_spoff = nullptr;
     int nd_max = 1;
     int32_t *d_idx = nullptr;
-    std::vector<int64_t> a_idx_off, b_idx_off;
+    std::vector<int64_t> a_idx_off, b_idx_off, bp_idx_off, cp_idx_off;
     int32_t *d_map = nullptr;
     std::vector<uint64_t> sparse_bits;
     // exchange codec round trip applied to one step's result (complex64 plans)

@@ -10,6 +10,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "device_util.h"
 
@@ -268,6 +270,60 @@ void launch_gather_leaves_impl(Dtype dt, int n_leaves, const LeafDesc *d_desc, c
     else
         hipLaunchKernelGGL((gather_leaves_kernel<Bf16Word>), grid, dim3(64), 0, st, d_desc, d_params,
                            (const Bf16Word *)leafdata, arena, maxw, expw, group_base, spoff);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ===================================================================== block copies (sparse state)
+//
+// Destination block j of slice s takes source block k = idx[j] - lo of that
+// slice when lo <= idx[j] < hi; otherwise it is zeroed (fill) or left alone.
+// Blocks hold `block` entries; each thread moves 16 bytes at a time.
+
+template <typename W>
+__global__ void __launch_bounds__(256) block_copy_kernel(const W *__restrict__ src, int64_t src_ss, W *__restrict__ dst,
+                                                         int64_t dst_ss, const int32_t *__restrict__ idx, int64_t lo,
+                                                         int64_t hi, int64_t block, int fill) {
+    const int64_t j = blockIdx.y;
+    const int s = blockIdx.z;
+    const int64_t k = (int64_t)idx[j] - lo;
+    const bool take = k >= 0 && k < hi - lo;
+    if (!take && !fill) return;
+    constexpr int V = 16 / sizeof(W);
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    W *d = dst + s * dst_ss + j * block;
+    const W *sp = src + s * src_ss + (take ? k : 0) * block;
+    if (block % V == 0) {
+        for (int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * V; e < block;
+             e += (int64_t)gridDim.x * blockDim.x * V) {
+            u4 v = {0u, 0u, 0u, 0u};
+            if (take) v = *(const u4 *)(sp + e);
+            *(u4 *)(d + e) = v;
+        }
+    } else {
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < block; e += (int64_t)gridDim.x * blockDim.x) {
+            W v{};
+            if (take) v = sp[e];
+            d[e] = v;
+        }
+    }
+}
+
+void launch_block_copy(Dtype dt, const void *src, int64_t src_ss, void *dst, int64_t dst_ss, const int32_t *idx,
+                       int64_t n_blocks, int64_t lo, int64_t hi, int64_t block, int S, bool fill, hipStream_t st) {
+    if (n_blocks <= 0 || S <= 0) return;
+    const int es = elem_bytes(dt);
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((block * es / 16 + 255) / 256, 64));
+    for (int64_t j0 = 0; j0 < n_blocks; j0 += 65535) {
+        const int64_t nb = std::min<int64_t>(65535, n_blocks - j0);
+        const dim3 grid(gx, (unsigned)nb, S);
+        uint8_t *d = (uint8_t *)dst + j0 * block * es;
+        if (dt == Dtype::C64)
+            hipLaunchKernelGGL((block_copy_kernel<uint2>), grid, dim3(256), 0, st, (const uint2 *)src, src_ss, (uint2 *)d,
+                               dst_ss, idx + j0, lo, hi, block, (int)fill);
+        else
+            hipLaunchKernelGGL((block_copy_kernel<uint32_t>), grid, dim3(256), 0, st, (const uint32_t *)src, src_ss,
+                               (uint32_t *)d, dst_ss, idx + j0, lo, hi, block, (int)fill);
+    }
     HIP_CHECK(hipGetLastError());
 }
 

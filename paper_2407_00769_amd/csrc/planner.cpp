@@ -7,6 +7,7 @@
 // [batch][m][k] and [batch][n][k] without a permute where possible, and
 // lays out the arena.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <numeric>
 
@@ -132,6 +133,23 @@ GemmShape step_gemm(const StepRec &st) {
     g.bk = st.bk;
     g.cm = st.cm;
     g.cn = st.cn;
+    return g;
+}
+
+GemmShape step_gemm_exec(const StepRec &st) {
+    GemmShape g = step_gemm(st);
+    if (st.scheme != 2) return g;
+    // n' = r N + n: r is the top part of the column index in B_P and C_P,
+    // whose blocks keep B's and C's own layouts
+    const int ln = ilog2_exact(st.N);
+    const int rb = ilog2_exact(st.N * st.K), rc = ilog2_exact(st.M * st.N);
+    g.N = st.N * st.mr;
+    g.nb = st.chunk;
+    g.bA = st.M * st.K;
+    g.bB = st.mr * st.N * st.K;
+    g.bC = st.mr * st.M * st.N;
+    g.bn = Seg{ln, st.bn.ls, rb};
+    g.cn = Seg{ln, st.cn.ls, rc};
     return g;
 }
 
@@ -596,6 +614,40 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             !derive_seg(Z.labels, st.m, st.cm) || !derive_seg(Z.labels, st.n, st.cn))
             TNC_THROW(TNC_EINVAL, "internal: operand layout has more than two runs per index");
         st.kernel = choose_kernel(an.dt, an.al, step_gemm(st));
+        if (an.sparse && st.a_mode == 2 && st.bn.l == 62 && st.cn.l == 62) {
+            // second scheme, when it moves fewer bytes: group the result
+            // blocks by the A block they read
+            const int64_t ndA = A.nd, ndZ = Z.nd;
+            std::vector<int32_t> cnt(ndA, 0), rpos(ndZ);
+            for (int64_t z = 0; z < ndZ; z++) rpos[z] = cnt[st.a_idx[z]]++;
+            int64_t mr = 1;
+            while (mr < *std::max_element(cnt.begin(), cnt.end())) mr *= 2;
+            const double sA_ = std::ldexp(1.0, A.rank()), sB_ = std::ldexp(1.0, B.rank()), sZ_ = std::ldexp(1.0, Z.rank());
+            const double bytes1 = (double)ndZ * (sA_ + sB_ + sZ_);
+            const double bytes2 = (double)ndA * sA_ + (double)ndA * mr * (3.0 * sB_ + sZ_) + 2.0 * (double)ndZ * sZ_;
+            const char *force = getenv("TNC_SPARSE_SCHEME");
+            const int want = force ? atoi(force) : 0;
+            if (mr >= 2 && (want == 2 || (want != 1 && bytes2 < 0.8 * bytes1))) {
+                st.scheme = 2;
+                st.mr = mr;
+                st.bp_idx.assign(ndA * mr, -1);
+                st.cp_idx.resize(ndZ);
+                for (int64_t z = 0; z < ndZ; z++) {
+                    const int64_t slot = (int64_t)st.a_idx[z] * mr + rpos[z];
+                    st.bp_idx[slot] = st.b_mode == 2 ? st.b_idx[z] : (st.b_mode == 0 ? (int32_t)z : 0);
+                    st.cp_idx[z] = (int32_t)slot;
+                }
+                // A blocks per chunk: B_P and C_P of one chunk within the
+                // larger of the result's own size and 2^24 entries
+                const double per_a = (double)mr * (sB_ + sZ_);
+                const double budget = std::max((double)ndZ * sZ_, std::ldexp(1.0, 24));
+                st.chunk = std::max<int64_t>(1, std::min<int64_t>(ndA, (int64_t)(budget / per_a)));
+                const char *cap = getenv("TNC_SPARSE_CHUNK");   // smaller chunks (tests)
+                if (cap && atoi(cap) > 0) st.chunk = std::min<int64_t>(st.chunk, atoi(cap));
+                st.kernel = choose_kernel(an.dt, an.al, step_gemm_exec(st));
+                st.bytes = es * bytes2;
+            }
+        }
         for (int l : st.beta) grp[l] = -1;
         for (int l : st.m) grp[l] = -1;
         for (int l : st.n) grp[l] = -1;
@@ -664,6 +716,7 @@ int64_t plan_memory(Analysis &an, int S, bool assign) {
     for (int i = 0; i < nT; i++)
         if (cls_t(i) == 0) off[i] = ar.alloc(bytes_of(an.tensors[i]));
     std::vector<int64_t> scr_a(an.steps.size(), -1), scr_b(an.steps.size(), -1);
+    std::vector<int64_t> scr_bp(an.steps.size(), -1), scr_cp(an.steps.size(), -1);
     auto run_step = [&](int s) {
         StepRec &st = an.steps[s];
         const TensorRec &A = an.tensors[st.a], &B = an.tensors[st.b], &Z = an.tensors[st.z];
@@ -671,6 +724,16 @@ int64_t plan_memory(Analysis &an, int S, bool assign) {
         if (pa) scr_a[s] = ar.alloc(bytes_of(A));
         if (pb) scr_b[s] = ar.alloc(bytes_of(B));
         off[st.z] = ar.alloc(bytes_of(Z));
+        int64_t bp_bytes = 0, cp_bytes = 0;
+        if (st.scheme == 2) {
+            const int64_t Sl = st.dep ? S : 1;
+            bp_bytes = (int64_t)es * st.chunk * st.mr * ((int64_t)1 << B.rank()) * Sl;
+            cp_bytes = (int64_t)es * st.chunk * st.mr * ((int64_t)1 << Z.rank()) * Sl;
+            scr_bp[s] = ar.alloc(bp_bytes);
+            scr_cp[s] = ar.alloc(cp_bytes);
+            ar.release(scr_cp[s], cp_bytes);
+            ar.release(scr_bp[s], bp_bytes);
+        }
         if (pa) ar.release(scr_a[s], bytes_of(A));
         if (pb) ar.release(scr_b[s], bytes_of(B));
         for (int t : {st.a, st.b}) {
@@ -707,6 +770,8 @@ int64_t plan_memory(Analysis &an, int S, bool assign) {
         for (size_t s = 0; s < an.steps.size(); s++) {
             an.steps[s].scr_a = scr_a[s];
             an.steps[s].scr_b = scr_b[s];
+            an.steps[s].scr_bp = scr_bp[s];
+            an.steps[s].scr_cp = scr_cp[s];
         }
     }
     return ar.peak;
@@ -723,6 +788,7 @@ void fill_stats(const Analysis &an, tnc_plan_stats &st) {
     st.peak_elems_per_slice = pe;
     const double passes = std::ldexp(1.0, an.n_recompute);
     st.n_recompute = an.n_recompute;
+    for (auto &s : an.steps) st.n_padded_steps += s.scheme == 2 ? 1 : 0;
     for (auto &s : an.steps) {
         if (s.dep) {
             const double w = s.inner ? passes : 1.0;

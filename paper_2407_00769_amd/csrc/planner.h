@@ -43,6 +43,16 @@ struct StepRec {
     // mode 0 the same d, 1 block 0 for every d, 2 the index array
     int a_mode = 0, b_mode = 0;
     std::vector<int32_t> a_idx, b_idx;
+    // second indexing scheme (the padded two-dimensional index): when many
+    // result blocks read the same A block, A is used as stored, one GEMM per
+    // A block against B_P, the B blocks of its mr result blocks side by side
+    // (index -1: a zero block), and C is taken out of the product C_P;
+    // A blocks are processed `chunk` at a time through scratch buffers
+    int scheme = 1;
+    int64_t mr = 1, chunk = 0;
+    std::vector<int32_t> bp_idx;      // per (A block, r): the B block, or -1
+    std::vector<int32_t> cp_idx;      // per result block: its block of C_P (A block * mr + r)
+    int64_t scr_bp = -1, scr_cp = -1; // arena offsets of the B_P and C_P chunks
     int kernel = K_NAIVE;
     double flops = 0;                 // per slice (or once, if invariant)
     double bytes = 0;                 // GEMM bytes per slice
@@ -98,6 +108,9 @@ bool derive_seg(const std::vector<int> &order, const std::vector<int> &idx, Seg 
 
 // GEMM descriptor of a step (slice strides zero).
 GemmShape step_gemm(const StepRec &st);
+// The GEMM the step actually launches: step_gemm, or for a step on the
+// second sparse-state scheme the per-A-block product with B_P (nb = chunk).
+GemmShape step_gemm_exec(const StepRec &st);
 
 // Default kernel choice for a step shape.
 int choose_kernel(Dtype dt, Algo al, const GemmShape &g);

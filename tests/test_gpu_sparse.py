@@ -99,3 +99,23 @@ def test_sparse_state_equals_dense_plan_on_a_subspace(T, ctx, case):
     assert metrics.fidelity(ref, osp) >= 1 - 1e-8
     T.tnc_plan_destroy(dense)
     T.tnc_plan_destroy(sparse)
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16_4m"])
+def test_second_scheme_with_chunks_equals_first(T, ctx, case, prec, monkeypatch):
+    """The padded two-dimensional index (B_P with -1 fill, C taken out of C_P),
+    a few A blocks per chunk, against the in-GEMM gathered index."""
+    n = 1 << len(case["sl"])
+    outs = {}
+    for scheme, chunk in (("1", None), ("2", "3")):
+        monkeypatch.setenv("TNC_SPARSE_SCHEME", scheme)
+        if chunk:
+            monkeypatch.setenv("TNC_SPARSE_CHUNK", chunk)
+        plan = T.tnc_plan_create_sparse(ctx, case["net"], case["ssa"], case["sl"], case["bits"], prec)
+        padded = T.tnc_plan_info(plan)["n_padded_steps"]
+        assert (padded > 0) == (scheme == "2"), padded
+        outs[scheme], _ = T.tnc_execute(plan, case["bits"], 0, n)
+        T.tnc_plan_destroy(plan)
+    tol = 1e-6 if prec == "c64" else 2e-2
+    assert metrics.rel_l2(outs["2"], outs["1"]) <= tol
+    assert metrics.fidelity(case["ref"], outs["2"]) >= (1 - 1e-8 if prec == "c64" else 0.999)
