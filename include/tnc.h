@@ -166,7 +166,10 @@ int tnc_slice_path(const tnc_network *net, int32_t n_steps, const int32_t *ssa_p
 
 /* ------------------------------------------------------------------ plan */
 
-/* Compile a path for execution on ctx's device.  Every step's GEMM kernel
+/* Compile a path for execution on ctx's device (paper Sec. 3.1: a
+ * sub-network and its pairwise contraction order, Alg. 1 "init"; slicing
+ * fixes the chosen labels, Sec. 3.1 global level; each step a permutation
+ * and a GEMM, Sec. 3.3 and 3.4.2).  Every step's GEMM kernel
  * variant is chosen by timing the candidates on the step's own operands
  * (environment: TNC_TUNE=0 keeps the shape-based default; TNC_TUNE_CACHE names
  * a file that persists the choices).
@@ -264,7 +267,10 @@ int tnc_plan_analyze_steps(const tnc_network *net, int32_t n_steps, const int32_
                            int32_t *kernel, int32_t *dep, int32_t *perm_ab, double *flops,
                            double *bytes);
 
-/* Sum the amplitudes of slices [slice_begin, slice_end) for each bitstring.
+/* Sum the amplitudes of slices [slice_begin, slice_end) for each bitstring
+ * (paper Sec. 3.1: the amplitude is the sum over the sliced sub-networks;
+ * Sec. 1 and 2.3: the bitstrings of one correlated subspace share the
+ * closed qubits and are read off the open-qubit tensor together).
  * bitstrings: host, n_bitstrings values; they must agree on every closed qubit
  *   (TNC_EINVAL otherwise); duplicates are allowed.
  * out_c128: 2*n_bitstrings doubles (re, im), host or device memory on the
