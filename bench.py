@@ -48,7 +48,8 @@ def log(*a):
 def kernel_family(kid):
     return {0: "gemm_naive", 1: "gemm_skinny", 2: "gemm_mfma_s", 3: "gemm_mfma_m", 4: "gemm_mfma_l",
             5: "gemm_mfma_w", 6: "gemm_mfma_xl", 7: "gemm_mfma_l2", 8: "gemm_dma_4",
-            9: "gemm_dma_8", 10: "gemm_dma_8w", 11: "gemm_dma_2", 12: "gemm_dma_n64", 13: "gemm_dma_n32", 14: "gemm_dma3_n64", 15: "gemm_dma3_2"}.get(int(kid), f"gemm_{kid}")
+            9: "gemm_dma_8", 10: "gemm_dma_8w", 11: "gemm_dma_2", 12: "gemm_dma_n64", 13: "gemm_dma_n32", 14: "gemm_dma3_n64", 15: "gemm_dma3_2",
+            16: "gemm_dmap_2", 17: "gemm_dmap_3"}.get(int(kid), f"gemm_{kid}")
 
 
 # ------------------------------------------------------------------ workloads
@@ -543,7 +544,7 @@ def sparse_study(torch, T, cn, workloads, n_bits=1024, cap=20, forms=("f16_4m", 
 
 # ------------------------------------------------------------------ learned cost model study
 
-def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3)):
+def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3, 4, 5)):
     """Step timings measured by the engine on random 12- to 30-qubit circuits
     under every form train the step-time MLP on the GPU; its held-out error is
     compared with the FLOP model's (one fitted scale), and the path search for
@@ -598,8 +599,12 @@ def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3)):
             nsl = 1 << len(sl)
             T.tnc_execute(plan, bits, 0, nsl)
             best = min(T.tnc_execute(plan, bits, 0, nsl)[1]["seconds"] for _ in range(5))
+            steps_ms, pred_ms = costmodel.path_prediction(ctx, plan, bits, nsl, "f16_4m")
+            search_ms = costmodel.search_estimate(ctx, net, ssa, sl, open_q)
             rec[name] = {"block_ms": round(best * 1e3, 3), "sliced": len(sl), "log2_flops": round(lc, 3),
-                         "search_s": round(t_search, 2)}
+                         "search_s": round(t_search, 2), "steps_ms": round(steps_ms, 3),
+                         "mlp_predicted_ms": round(pred_ms, 3),
+                         "mlp_search_estimate_ms": round(search_ms, 3)}
             T.tnc_plan_destroy(plan)
         rec["gain"] = round(rec["flop"]["block_ms"] / rec["mlp"]["block_ms"], 4)
         runs.append(rec)

@@ -95,3 +95,49 @@ def flop_model_fit(flops, y):
 
 def flop_model_predict(flops, c):
     return np.log2(np.maximum(flops, 1.0)) + c
+
+
+def path_prediction(ctx, plan, bits, n_slices, prec):
+    """Measured and MLP-predicted device time (ms) of one execute of
+    [0, n_slices): every launch's features go through the trained model and
+    the predicted per-launch times are summed, so the model is judged at the
+    level of whole paths as well as single steps."""
+    info = T.tnc_plan_info(plan)
+    n_steps = info["n_steps"]
+    steps = T.tnc_plan_steps(plan, n_steps)
+    T.tnc_plan_set_timing(plan, True)
+    T.tnc_execute(plan, bits, 0, n_slices)
+    g, p, launches = T.tnc_plan_step_times(plan, n_steps)
+    T.tnc_plan_set_timing(plan, False)
+    X, mult, measured = [], [], 0.0
+    for i in range(n_steps):
+        if launches[i] == 0:
+            continue
+        per_launch_slices = n_slices / launches[i] if steps["dep"][i] else 1.0
+        m, n, k, b = steps["log2_mnkb"][i]
+        sa, sb = steps["perm_ab"][i]
+        X.append([m, n, k, b + math.log2(per_launch_slices), sa, sb, DTYPE_CODE[prec], ALGO_CODE[prec]])
+        mult.append(float(launches[i]))
+        measured += float(g[i] + p[i])
+    pred = T.tnc_mlp_predict(ctx, np.array(X, np.float32))
+    return measured, float(np.sum(np.exp2(pred.astype(np.float64)) * np.array(mult)) * 1e-3)
+
+
+def search_estimate(ctx, net, ssa, sliced, open_q, prec="f16_4m", batch_cap=64):
+    """The model's cost of a path as the path search forms it (ms): each
+    step's features with up to batch_cap slices per launch, times the launches
+    the slices need; the same sum the search minimises."""
+    a = T.tnc_plan_analyze_steps(net, ssa, sliced, open_q, prec)
+    total = 1 << len(sliced)
+    S = min(total, batch_cap)
+    X, mult = [], []
+    for i in range(len(a["flops"])):
+        if a["flops"][i] <= 0:   # entries past the device steps (host-absorbed pairs run no launch)
+            continue
+        m, n, k, b = a["log2_mnkb"][i]
+        dep = bool(a["dep"][i])
+        sa, sb = a["perm_ab"][i]
+        X.append([m, n, k, b + (math.log2(S) if dep else 0.0), sa, sb, DTYPE_CODE[prec], ALGO_CODE[prec]])
+        mult.append(total / S if dep else 1.0)
+    pred = T.tnc_mlp_predict(ctx, np.array(X, np.float32))
+    return float(np.sum(np.exp2(pred.astype(np.float64)) * np.array(mult)) * 1e-3)
