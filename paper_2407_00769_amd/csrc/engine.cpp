@@ -463,6 +463,14 @@ void tune_cache_append(const TuneKey &k, int kid) {
 }
 
 double autotune_plan(tnc_plan *p) {
+    // TNC_FORCE_KERNEL=<id>: every step that variant supports runs it, untimed
+    // (tests of one variant over whole plans)
+    if (const char *force = getenv("TNC_FORCE_KERNEL")) {
+        const int f = atoi(force);
+        for (size_t si = 0; si < p->an.steps.size(); si++)
+            if (gemm_supported(f, p->an.dt, p->an.al, plan_step_shape(p, (int)si))) p->an.steps[si].kernel = f;
+        return 0.0;
+    }
     const char *env = getenv("TNC_TUNE");
     if (env && env[0] == '0') return 0.0;
     Analysis &an = p->an;
@@ -526,7 +534,7 @@ double autotune_plan(tnc_plan *p) {
         std::vector<int> cands;
         // big steps: only the large matrix-core tiles are worth timing
         const bool big = rec.flops * (double)Sl > 1e13;
-        static const int big_order[] = {K_DMA_8,   K_DMA_8W,  K_DMA_4,   K_DMA_2,   K_DMA_N64, K_DMA_N32,
+        static const int big_order[] = {K_DMA_8,   K_DMA_8W,   K_DMA_4,  K_DMA_2,   K_DMAP_2,  K_DMA_N64, K_DMA_N32,
                                         K_DMA3_N64, K_DMA3_2, K_MFMA_XL, K_MFMA_L2, K_MFMA_L};
         if (big) {
             for (int k : big_order)

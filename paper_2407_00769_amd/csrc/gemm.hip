@@ -803,8 +803,7 @@ struct DTile {
     static constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
     static constexpr int RING_BYTES = STAGES * STAGE_BYTES;
-    static constexpr int C_BYTES = BM * BN * 4;
-    static constexpr int LDS_BYTES = RING_BYTES > C_BYTES ? RING_BYTES : C_BYTES;
+    static constexpr int LDS_BYTES = RING_BYTES;                  // the result leaves from registers
     static constexpr int WTM = BM / WM, WTC = BN / WN;          // rows, complex columns per wave
     static constexpr int FM = WTM / 32, FC = WTC / 32;
     static constexpr int A_PER = BM / 8 / (NT / 64);             // 1 KB DMA blocks per wave and stage
@@ -859,6 +858,83 @@ __device__ __forceinline__ void planes3m(const u32x4 &w0, const u32x4 &w1, u32x4
         const h2 sum = __builtin_bit_cast(h2, r) + __builtin_bit_cast(h2, i);
         sm[q] = __builtin_bit_cast(uint32_t, sum);
     }
+}
+
+// ---- result tile straight from the accumulators (no LDS)
+// Register group q (r = 4q..4q+3) of a 32 x 32 accumulator block holds rows
+// 8q + 4(l/32) + 0..3 of column l%32 in lane l.  With C chunked along m those
+// four rows are one 16-byte run of C.  With C chunked along n, a 4 x 4
+// transpose within each quad of lanes (two exchange rounds of DPP quad
+// permutes) leaves lane l with row 8q + 4(l/32) + l%4 and columns
+// 4((l%32)/4)..+3: again one 16-byte run, and one store instruction writes
+// eight whole 128-byte lines.
+template <int CTRL> __device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ void quad_transpose(uint32_t (&w)[4], int lane) {
+    const bool b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    // swap the off-diagonal 2 x 2 blocks with the lane two over (quad_perm 2,3,0,1)
+    const uint32_t t0 = quad_perm<0x4E>(w[0]), t1 = quad_perm<0x4E>(w[1]);
+    const uint32_t t2 = quad_perm<0x4E>(w[2]), t3 = quad_perm<0x4E>(w[3]);
+    const uint32_t a0 = b1 ? t2 : w[0], a1 = b1 ? t3 : w[1], a2 = b1 ? w[2] : t0, a3 = b1 ? w[3] : t1;
+    // transpose each 2 x 2 block with the lane one over (quad_perm 1,0,3,2)
+    const uint32_t u0 = quad_perm<0xB1>(a0), u1 = quad_perm<0xB1>(a1);
+    const uint32_t u2 = quad_perm<0xB1>(a2), u3 = quad_perm<0xB1>(a3);
+    w[0] = b0 ? u1 : a0;
+    w[1] = b0 ? a1 : u0;
+    w[2] = b0 ? u3 : a2;
+    w[3] = b0 ? a3 : u2;
+}
+
+// Scales, rounds and stores a wave's FM x FC accumulator blocks (4M: real and
+// imaginary sets; 3M: T1, T2, T3) whose first row and column are r0, c0 (r0 a
+// multiple of 64, c0 of 32); returns the lane's largest stored |re|, |im|
+// (NaN as +inf).  The row and column of an entry are sums of bit-disjoint
+// parts (tile origin, block, group, lane), so its offset is one per-lane base
+// plus a wave-uniform offset per group.
+template <typename W, bool M3, int FM, int FC, int NACC>
+__device__ __forceinline__ float store_tile(const floatx16 (&acc)[FM][FC][NACC], float scale, uint32_t *Cp,
+                                            const GemmShape &g, int64_t r0, int64_t c0, int lane) {
+    const bool nc = g.c_nc != 0;
+    const int64_t lr = 4 * (lane >> 5) + (nc ? (lane & 3) : 0);
+    const int64_t lc = nc ? (lane & 28) : (lane & 31);
+    uint32_t *base = Cp + seg_offset(g.cm, r0 + lr) + seg_offset(g.cn, c0 + lc);
+    float mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FC; j++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int r = 4 * q + e;
+                    float re, im;
+                    if constexpr (M3) {
+                        re = acc[i][j][0][r] - acc[i][j][1][r];
+                        im = acc[i][j][2][r] - acc[i][j][0][r] - acc[i][j][1][r];
+                    } else {
+                        re = acc[i][j][0][r];
+                        im = acc[i][j][1][r];
+                    }
+                    w[e] = Pack<W>::make(re * scale, im * scale).w;
+                }
+                if (nc) quad_transpose(w, lane);
+                u32x4 v;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    v[e] = w[e];
+                    const float2 f = unpack(W{w[e]});
+                    mx = fmaxf(mx, absmax_nan(f.x, f.y));
+                }
+                const int64_t uo = seg_offset(g.cm, i * 32 + 8 * q) + seg_offset(g.cn, j * 32);
+                *(u32x4 *)(base + uo) = v;
+                // one group at a time: the compiler would otherwise interleave
+                // all of them and run out of registers
+                __builtin_amdgcn_sched_barrier(0);
+            }
+    return mx;
 }
 
 template <bool BF, bool M3, int BM, int BN, int WM, int WN, int STAGES>
@@ -1059,8 +1135,6 @@ __global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAG
         xform(fb1, re1, im1);
         madd(fa1, re1, im1);
     }
-    ring_wait<0>();   // every wave is done with the ring before it is reused
-
     if (P > 1) {
         float2 *pp = g.part + ((s * g.nb + b) * P + part) * g.M * g.N;
 #pragma unroll
@@ -1075,42 +1149,273 @@ __global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAG
                 }
         return;
     }
-    // epilogue: scale, round, stage the tile as complex words [BM][BN], write out
-    uint32_t *Cw = (uint32_t *)smem;
+    // epilogue: scale, round and store from the accumulators (the last
+    // stage's wait left no DMA in flight, and LDS is not touched again)
+    const float mx = store_tile<W, M3>(acc, scale, Cp, g, m0 + wm * WTM, n0 + wn * WTC, lane);
+    finish_max<true>(sc, s, mx);
+}
+
+// ===================================================================== persistent LDS-DMA 4M (short k)
+//
+// The short-k steps (K = 2^6..2^9 complex) write a large C per tile, and a
+// one-tile block fills its ring from empty once per tile.  Here two blocks
+// per CU (two-stage rings) each walk a list of tiles (all slices and
+// inner-batch entries of the launch) and the DMA ring runs on across tile
+// boundaries: the first stage of tile j+1 is in flight while tile j's last
+// stage is multiplied and its result is stored (straight from the
+// accumulators), and the waits never cover the stores unless a later stage
+// needs them to.  Measured against the one-tile kernel on the same tile it
+// is level on K = 2^7 and 5-10% slower on K = 2^9; the autotuner picks.
+//
+// Vector-memory ordering: the ring wait counts every vector memory
+// instruction issued after the awaited stage's loads -- the later stages'
+// loads and, when a tile ended in between, that tile's stores -- relying on
+// vmcnt retiring loads and stores in issue order.
+//
+// Tile order: block i (on XCD i % 8) takes items i, i + G, i + 2G, ...
+// (G = blocks in the grid, a multiple of 8); within each window of G items
+// the XCD's blocks take one run of G / 8 consecutive items, so the tiles an
+// XCD holds at once form a patch of row and column blocks of one slice.
+
+template <int BM, int BN, int WM, int WN, int STAGES>
+struct PTile {
+    using D = DTile<BM, BN, WM, WN, 2>;
+    static constexpr int NT = D::NT, BK = D::BK;
+    static constexpr int STAGE_BYTES = D::STAGE_BYTES;
+    static constexpr int RING_BYTES = STAGES * STAGE_BYTES;
+    static constexpr int LDS_BYTES = RING_BYTES;                 // the result leaves from registers
+    static constexpr int NS = D::FM * D::FC * 4;                 // 16-byte stores per thread and tile
+    static constexpr int LPT = D::LPT;
+    // two blocks per CU when two rings fit in LDS
+    static constexpr int BLOCKS_PER_CU = 2 * LDS_BYTES <= 160 * 1024 ? 2 : 1;
+    static_assert((STAGES - 2) * LPT + NS < 64, "vmcnt range");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+// wait until at most VM vector memory instructions are outstanding (VM = 63:
+// no vector memory wait), LDS traffic done, then the block barrier
+template <int STAGES, int LPT, int NS>
+__device__ __forceinline__ void pring_wait(int ahead, bool epi) {
+    // ahead in [0, STAGES - 2]
+    if constexpr (STAGES == 2) {
+        if (epi) ring_wait<NS>();
+        else ring_wait<0>();
+    } else if constexpr (STAGES == 3) {
+        if (ahead == 1) {
+            if (epi) ring_wait<LPT + NS>();
+            else ring_wait<LPT>();
+        } else {
+            if (epi) ring_wait<NS>();
+            else ring_wait<0>();
+        }
+    } else {
+        static_assert(STAGES == 2 || STAGES == 3, "stages");
+    }
+}
+
+template <bool BF, int BM, int BN, int WM, int WN, int STAGES>
+__global__ void __launch_bounds__(64 * WM * WN, (PTile<BM, BN, WM, WN, STAGES>::BLOCKS_PER_CU))
+    gemm_dmap_h_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t *__restrict__ C,
+                       GemmShape g, ScaleRefs sc, int S) {
+    using Pt = PTile<BM, BN, WM, WN, STAGES>;
+    using Tl = DTile<BM, BN, WM, WN, 2>;
+    using W = typename std::conditional<BF, Bf16Word, HalfWord>::type;
+    constexpr int NT = Pt::NT, FM = Tl::FM, FC = Tl::FC, WTM = Tl::WTM, WTC = Tl::WTC, BK = Pt::BK;
+    constexpr int LPT = Pt::LPT, NS = Pt::NS;
+    extern __shared__ __align__(16) uint8_t smem[];
+
+    const int64_t tiles_n = g.N / BN, tiles_m = g.M / BM, tiles = tiles_m * tiles_n;
+    const int64_t total = (int64_t)S * g.nb * tiles;
+    const int64_t G = gridDim.x, bi = blockIdx.x;
+    if (bi >= total) return;
+    const int64_t n_items = (total - bi + G - 1) / G;
+    const int nk = (int)(g.K / BK);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int dq = (lane & 7) ^ (lane >> 3);
+
+    // item j of this block -> (slice, batch entry, tile origin)
+    struct Item {
+        int s;
+        int64_t b, m0, n0;
+    };
+    auto item_of = [&](int64_t j) {
+        const int64_t w0 = j * G;
+        int64_t idx = w0 + bi;
+        if (w0 + G <= total && (G & 7) == 0) idx = w0 + (bi & 7) * (G >> 3) + (bi >> 3);
+        Item it;
+        const int64_t t = idx % tiles, rest = idx / tiles;
+        it.b = rest % g.nb;
+        it.s = (int)(rest / g.nb);
+        int64_t mt, nt;
+        tile_coords<4>(t, tiles_m, tiles_n, mt, nt);
+        it.m0 = mt * BM;
+        it.n0 = nt * BN;
+        return it;
+    };
+    // DMA row pointers of an item (lane part folded in, as in the one-tile kernel)
+    struct Ptrs {
+        const uint32_t *pa[Tl::A_PER], *pb[Tl::B_PER];
+    };
+    auto ptrs_of = [&](const Item &it) {
+        Ptrs p;
+        const uint32_t *Ap = A + it.s * g.sA + a_block(g, it.b) * g.bA;
+        const uint32_t *Bp = B + it.s * g.sB + b_block(g, it.b) * g.bB;
 #pragma unroll
-    for (int i = 0; i < FM; i++)
+        for (int i = 0; i < Tl::A_PER; i++)
+            p.pa[i] = Ap + seg_offset(g.am, it.m0 + 8 * (wave + i * (NT / 64)) + (lane >> 3)) + seg_offset(g.ak, 4 * dq);
+#pragma unroll
+        for (int i = 0; i < Tl::B_PER; i++)
+            p.pb[i] = Bp + seg_offset(g.bn, it.n0 + 8 * (wave + i * (NT / 64)) + (lane >> 3)) + seg_offset(g.bk, 4 * dq);
+        return p;
+    };
+    auto issue = [&](const Ptrs &p, int64_t q, int kt) {
+        uint8_t *base = smem + (int)(q % STAGES) * Pt::STAGE_BYTES;
+        const int64_t k0 = (int64_t)kt * BK;
+        const int64_t ka = seg_offset(g.ak, k0), kb = seg_offset(g.bk, k0);
+#pragma unroll
+        for (int i = 0; i < Tl::A_PER; i++)
+            __builtin_amdgcn_global_load_lds((const void *)(p.pa[i] + ka),
+                                             (__attribute__((address_space(3))) void *)(base + (wave + i * (NT / 64)) * 1024),
+                                             16, 0, 0);
+#pragma unroll
+        for (int i = 0; i < Tl::B_PER; i++)
+            __builtin_amdgcn_global_load_lds((const void *)(p.pb[i] + kb),
+                                             (__attribute__((address_space(3))) void *)(base + Tl::A_BYTES +
+                                                                                        (wave + i * (NT / 64)) * 1024),
+                                             16, 0, 0);
+    };
+
+    const int f_s0 = (lane >> 5) ^ (lane & 7);
+    int a_off[BK / 8], b_off[BK / 8];
+#pragma unroll
+    for (int kk = 0; kk < BK / 8; kk++) {
+        a_off[kk] = (wm * WTM + (lane & 31)) * 128 + ((kk << 1) ^ f_s0) * 16;
+        b_off[kk] = Tl::A_BYTES + (wn * WTC + (lane & 31)) * 128 + ((kk << 1) ^ f_s0) * 16;
+    }
+    floatx16 acc[FM][FC][2];
+    auto load = [&](const uint8_t *sb, int kk, u32x4 (&fa)[FM], u32x4 (&fb)[FC]) {
+#pragma unroll
+        for (int i = 0; i < FM; i++) fa[i] = *(const u32x4 *)(sb + a_off[kk] + i * 32 * 128);
+#pragma unroll
+        for (int j = 0; j < FC; j++) fb[j] = *(const u32x4 *)(sb + b_off[kk] + j * 32 * 128);
+    };
+    auto xform = [&](const u32x4 (&fb)[FC], u32x4 (&bre)[FC], u32x4 (&bim)[FC]) {
 #pragma unroll
         for (int j = 0; j < FC; j++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                int row = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                int col = wn * WTC + j * 32 + (lane & 31);
-                Cw[row * BN + col] = Pack<W>::make(c_re(i, j, r) * scale, c_im(i, j, r) * scale).w;
+            for (int q = 0; q < 4; q++) {
+                bre[j][q] = fb[j][q] ^ 0x80000000u;
+                bim[j][q] = __builtin_amdgcn_perm(fb[j][q], fb[j][q], 0x01000302u);
             }
-    __syncthreads();
-    float mx = 0.f;
-    constexpr int C_CHUNKS = BM * BN / 4;
-    for (int c = tid; c < C_CHUNKS; c += NT) {
-        u32x4 v;
-        int row, col;
-        if (g.c_nc) {
-            row = c / (BN / 4);
-            col = (c % (BN / 4)) * 4;
-            v = *(const u32x4 *)(Cw + row * BN + col);
-        } else {
-            col = c / (BM / 4);
-            row = (c % (BM / 4)) * 4;
+    };
+    auto madd = [&](const u32x4 (&fa)[FM], const u32x4 (&bre)[FC], const u32x4 (&bim)[FC]) {
 #pragma unroll
-            for (int q = 0; q < 4; q++) v[q] = Cw[(row + q) * BN + col];
+        for (int j = 0; j < FC; j++)
+#pragma unroll
+            for (int i = 0; i < FM; i++) {
+                acc[i][j][0] = mfma16<BF>(fa[i], bre[j], acc[i][j][0]);
+                acc[i][j][1] = mfma16<BF>(fa[i], bim[j], acc[i][j][1]);
+            }
+    };
+    static_assert(BK / 8 == 4, "four k-steps per stage");
+
+    Item cur = item_of(0);
+    Ptrs pc = ptrs_of(cur), pn = pc;
+    Item nxt = cur;
+    if (n_items > 1) {
+        nxt = item_of(1);
+        pn = ptrs_of(nxt);
+    }
+    const int64_t Q = n_items * nk;
+#pragma unroll
+    for (int st = 0; st < STAGES - 1; st++)
+        if (st < Q) issue(pc, st, st);   // nk >= STAGES - 1: all in item 0
+
+    float mx = 0.f;           // running max of the stored values of slice cur.s
+    int mx_slice = cur.s;
+    auto flush = [&]() {
+        float v = wave_max(mx);
+        if (lane == 0) {
+            atomicMax(&sc.maxC[mx_slice], __float_as_uint(v));
+            if (!(v <= sc.flag_above) && sc.flag) atomicOr(sc.flag, 1u);
         }
-        *(u32x4 *)(Cp + c_index(g, m0 + row, n0 + col)) = v;
+        mx = 0.f;
+    };
+
+    for (int64_t j = 0; j < n_items; j++) {
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            float2 f = unpack(W{v[q]});
-            mx = fmaxf(mx, absmax_nan(f.x, f.y));
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+            for (int jj = 0; jj < FC; jj++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    acc[i][jj][0][r] = 0.f;
+                    acc[i][jj][1][r] = 0.f;
+                }
+        const int64_t q0 = j * nk;
+        for (int kt = 0; kt < nk; kt++) {
+            const int64_t q = q0 + kt;
+            {
+                const int64_t later = Q - 1 - q;
+                const int ahead = (int)(later < STAGES - 2 ? later : STAGES - 2);
+                // the previous tile's stores went out after this stage's loads
+                const bool epi = j > 0 && kt <= STAGES - 2;
+                pring_wait<STAGES, LPT, NS>(ahead, epi);
+            }
+            {
+                const int64_t qi = q + STAGES - 1;
+                if (qi < Q) {
+                    const int kti = kt + STAGES - 1;
+                    if (kti < nk) issue(pc, qi, kti);
+                    else issue(pn, qi, kti - nk);
+                }
+            }
+            const uint8_t *sb = smem + (int)(q % STAGES) * Pt::STAGE_BYTES;
+            u32x4 fa0[FM], fb0[FC], re0[FC], im0[FC], fa1[FM], fb1[FC], re1[FC], im1[FC];
+            load(sb, 0, fa0, fb0);
+            xform(fb0, re0, im0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(sb, 1, fa1, fb1);
+            __builtin_amdgcn_sched_barrier(0);
+            madd(fa0, re0, im0);
+            __builtin_amdgcn_sched_barrier(0);
+            xform(fb1, re1, im1);
+            __builtin_amdgcn_sched_barrier(0);
+            load(sb, 2, fa0, fb0);
+            __builtin_amdgcn_sched_barrier(0);
+            madd(fa1, re1, im1);
+            __builtin_amdgcn_sched_barrier(0);
+            xform(fb0, re0, im0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(sb, 3, fa1, fb1);
+            __builtin_amdgcn_sched_barrier(0);
+            madd(fa0, re0, im0);
+            __builtin_amdgcn_sched_barrier(0);
+            xform(fb1, re1, im1);
+            madd(fa1, re1, im1);
+        }
+        // ---- tile done: scale and store (the stores drain under the next tile)
+        const int shift = step_shift(sc, cur.s);
+        if (cur.b == 0 && cur.m0 == 0 && cur.n0 == 0 && tid == 0) record_exponent(sc, cur.s, shift);
+        const float scale = pow2_neg(shift);
+        if (cur.s != mx_slice) {
+            flush();
+            mx_slice = cur.s;
+        }
+        uint32_t *Cp = C + cur.s * g.sC + cur.b * g.bC;
+        mx = fmaxf(mx, store_tile<W, false>(acc, scale, Cp, g, cur.m0 + wm * WTM, cur.n0 + wn * WTC, lane));
+        if (j + 1 < n_items) {
+            cur = nxt;
+            pc = pn;
+            if (j + 2 < n_items) {
+                nxt = item_of(j + 2);
+                pn = ptrs_of(nxt);
+            }
         }
     }
-    finish_max<true>(sc, s, mx);
+    flush();
 }
 
 // ===================================================================== matrix cores, complex64 4M
@@ -1368,6 +1673,7 @@ const char *kernel_name(int k) {
         case K_DMA_N32: return "dma_n32";
         case K_DMA3_N64: return "dma3_n64";
         case K_DMA3_2: return "dma3_2";
+        case K_DMAP_2: return "dmap_2";
         default: return "?";
     }
 }
@@ -1400,6 +1706,7 @@ static TileCfg tile_of(int kid, Dtype dt, Algo al) {
             case K_DMA_2: return {128, 128};
             case K_DMA_N64: return {256, 64};
             case K_DMA_N32: return {256, 32};
+            case K_DMAP_2: return {128, 128};
         }
     } else {
         switch (kid) {
@@ -1428,6 +1735,12 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
     if (dt == Dtype::C64 && al == Algo::M3) return false;
     if (kid >= K_DMA_4 && kid <= K_DMA_N32) {
         // 16-bit 4M, both operands chunked along k, whole tiles and k-tiles
+        if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
+        if (g.K % 32) return false;
+    }
+    if (kid == K_DMAP_2) {
+        // the persistent tile loop: as the DMA kernels (a two-stage ring spans
+        // two tiles at most for any whole number of k-tiles)
         if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
         if (g.K % 32) return false;
     }
@@ -1472,8 +1785,13 @@ static void launch_valu(int kid, Algo al, const void *A, const void *B, void *C,
     const Dtype dt = sizeof(W) == 8 ? Dtype::C64 : Dtype::F16;
     const int mode = thin_mode(dt, g);
     if (mode >= 0) {
+        // about 4096 blocks in all (two rounds of eight per CU): each thread
+        // then walks many row units, so the B columns a block stages in LDS
+        // serve many rows
         const int64_t units = mode == 0 ? g.M : g.M / (16 / (int64_t)sizeof(W));
-        dim3 tg((unsigned)std::min<int64_t>((units + 255) / 256, 2048), (unsigned)(g.nb * nch), S);
+        const int64_t others = g.nb * nch * (int64_t)S;
+        const int64_t gx = std::max<int64_t>(1, std::min<int64_t>({(units + 255) / 256, 2048, (4096 + others - 1) / others}));
+        dim3 tg((unsigned)gx, (unsigned)(g.nb * nch), S);
 #define THIN(NNV)                                                                                          \
     do {                                                                                                   \
         if (mode == 0) {                                                                                   \
@@ -1554,9 +1872,38 @@ static void launch_dma_cfg(const void *A, const void *B, void *C, const GemmShap
                        (uint32_t *)C, g, sc);
 }
 
+// One or two blocks per CU (as many as their rings fit in LDS), each walking
+// its share of the launch's S x nb x tiles items (the grid a multiple of 8 so
+// that the XCD patches line up).
+template <bool BF, int BM, int BN, int WM, int WN, int STAGES>
+static void launch_dmap_cfg(const void *A, const void *B, void *C, const GemmShape &g, int S, const ScaleRefs &sc,
+                            hipStream_t st) {
+    using Pt = PTile<BM, BN, WM, WN, STAGES>;
+    auto kern = gemm_dmap_h_kernel<BF, BM, BN, WM, WN, STAGES>;
+    static bool attr = false;
+    if (!attr) {
+        HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, Pt::LDS_BYTES));
+        attr = true;
+    }
+    static int n_cu = 0;
+    if (!n_cu) {
+        int dev = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        HIP_CHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        if (n_cu < 1) n_cu = 1;
+    }
+    if (g.split != 1) TNC_THROW(TNC_EINVAL, "internal: the persistent tile loop takes no split-K");
+    const int64_t total = (int64_t)S * g.nb * (g.M / BM) * (g.N / BN);
+    int64_t G = std::min<int64_t>(total, (int64_t)n_cu * Pt::BLOCKS_PER_CU);
+    if (G >= 8) G &= ~(int64_t)7;
+    hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(Pt::NT), Pt::LDS_BYTES, st, (const uint32_t *)A,
+                       (const uint32_t *)B, (uint32_t *)C, g, sc, S);
+}
+
 template <bool BF>
 static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, const GemmShape &g, int S,
                      const ScaleRefs &sc, hipStream_t st) {
+    if (kid == K_DMAP_2) return launch_dmap_cfg<BF, 128, 128, 2, 2, 2>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_4) return launch_dma_cfg<BF, 256, 128, 2, 2, 3>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_8) return launch_dma_cfg<BF, 256, 128, 4, 2, 3>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_8W) return launch_dma_cfg<BF, 256, 128, 2, 4, 3>(A, B, C, g, S, sc, st);
@@ -1616,6 +1963,7 @@ static void launch_c64(int kid, const void *A, const void *B, void *C, const Gem
 
 int64_t splitk_factor(int kid, Dtype dt, Algo al, const GemmShape &g, int S) {
     if (kid < K_MFMA_S || kid >= K_COUNT || !gemm_supported(kid, dt, al, g)) return 1;
+    if (kid == K_DMAP_2) return 1;
     TileCfg t = tile_of(kid, dt, al);
     const int64_t bk = dt == Dtype::C64 ? 16 : 32;
     const int64_t blocks = (g.M / t.BM) * (g.N / t.BN) * g.nb * (int64_t)S;

@@ -104,7 +104,7 @@ def _check_contract(T, ctx, prec, nb, m, n, k, seed, scale_log2=0):
 
 KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5, "mfma_xl": 6,
            "mfma_l2": 7, "dma_4": 8, "dma_8": 9, "dma_8w": 10, "dma_2": 11, "dma_n64": 12, "dma_n32": 13,
-           "dma3_n64": 14, "dma3_2": 15}
+           "dma3_n64": 14, "dma3_2": 15, "dmap_2": 16}
 SHAPES = [  # nb, m, n, k  (log2)
     (0, 9, 6, 5), (1, 8, 5, 3), (0, 10, 4, 6), (2, 7, 7, 4), (0, 8, 0, 2), (0, 6, 3, 0), (0, 12, 5, 7),
     (0, 9, 8, 6), (1, 8, 7, 5),
@@ -119,6 +119,21 @@ def test_contract_kernels(T, ctx, prec, kname, monkeypatch):
     monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
     for i, (nb, m, n, k) in enumerate(SHAPES):
         _check_contract(T, ctx, prec, nb, m, n, k, seed=100 + i)
+
+
+# shapes with more tiles than the persistent kernel has blocks (256 CUs): each
+# block walks two tiles and the ring runs on across their ends; k from one
+# 32-wide stage per tile to sixteen, and one batched case (the oracle's einsum
+# is slow on batch labels, so that one stays small)
+PERSISTENT_SHAPES = [(0, 14, 9, 5), (0, 13, 10, 6), (0, 15, 8, 7), (0, 12, 9, 9), (2, 11, 8, 5)]
+
+
+@pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m"])
+@pytest.mark.parametrize("kname", ["dmap_2"])
+def test_persistent_tile_loop(T, ctx, prec, kname, monkeypatch):
+    monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
+    for i, (nb, m, n, k) in enumerate(PERSISTENT_SHAPES):
+        _check_contract(T, ctx, prec, nb, m, n, k, seed=300 + i)
 
 
 def _oriented_case(rng, m, n, k, a_kc, b_kc, c_nc):
@@ -330,6 +345,45 @@ def test_execute_rejects_bad_calls(T, ctx):
     assert e.value.code == -2
     T.tnc_destroy(c2)
     T.tnc_network_destroy(net)
+
+
+@pytest.mark.parametrize("kname", ["dmap_2"])
+def test_config2_block_with_persistent_tiles(T, ctx, kname, monkeypatch):
+    """The 30-qubit block with the persistent tile loop forced on every step
+    it supports: 256 slices in one launch (the tiles of all slices walked by
+    one grid), ragged slice groups, against the stored oracle amplitudes with
+    the FP16 bounds of the full-block test."""
+    ref = np.load(os.path.join(GOLD, "config2_amplitudes.npy"))
+    from paper_2407_00769_amd import circuit_network as cn
+    c = workloads.config_circuit(2)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    open_q = list(range(20, 30))
+    for seed in range(1, 20):
+        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 22, restarts=64, seed=seed)
+        if len(sl) == 8:
+            break
+    bits = workloads.prefix_bitstrings(30, open_q, 1024, 3)
+    ws = torch.empty(16 << 30, dtype=torch.uint8, device="cuda:0")
+    big = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
+    plan = T.tnc_plan_create(big, net, ssa, sl, open_q, "f16_4m")
+    info = T.tnc_plan_info(plan)
+    steps = T.tnc_plan_steps(plan, info["n_steps"])
+    n_forced = int(np.sum(steps["kernel"] == KERNELS[kname]))
+    assert n_forced >= 1, n_forced
+    out, _ = T.tnc_execute(plan, bits, 0, 256)
+    f, rl, rm = metrics.fidelity(ref, out), metrics.rel_l2(out, ref), metrics.rel_max(out, ref)
+    print(kname, n_forced, "steps; fidelity", f, "rel_l2", rl, "rel_max", rm)
+    assert f >= 0.999 and rl <= 0.03 and rm <= 0.06, (f, rl, rm)
+    parts = [T.tnc_execute(plan, bits, a, b)[0] for a, b in ((0, 3), (3, 5), (5, 256))]
+    np.testing.assert_allclose(sum(parts), out, rtol=0, atol=1e-12 * np.max(np.abs(out)))
+    T.tnc_plan_destroy(plan)
+    T.tnc_destroy(big)
+    T.tnc_network_destroy(net)
+    del ws
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("prec", ["c64", "f16_4m", "f16_3m", "bf16_4m"])
