@@ -569,7 +569,8 @@ def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3, 4, 5))
     perm = rng.permutation(n)
     tr, te = perm[: int(0.8 * n)], perm[int(0.8 * n):]
     t0 = time.perf_counter()
-    loss = T.tnc_mlp_train(ctx, X[tr], y[tr], epochs=60, batch=256, lr=2e-3, seed=7)
+    Xw, yw = costmodel.weighted_rows(X[tr], y[tr])
+    loss = T.tnc_mlp_train(ctx, Xw, yw, epochs=40, batch=256, lr=2e-3, seed=7)
     t_train = time.perf_counter() - t0
     pred = T.tnc_mlp_predict(ctx, X[te])
     cfit = costmodel.flop_model_fit(fl[tr], y[tr])
@@ -600,7 +601,8 @@ def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3, 4, 5))
             T.tnc_execute(plan, bits, 0, nsl)
             best = min(T.tnc_execute(plan, bits, 0, nsl)[1]["seconds"] for _ in range(5))
             steps_ms, pred_ms = costmodel.path_prediction(ctx, plan, bits, nsl, "f16_4m")
-            search_ms = costmodel.search_estimate(ctx, net, ssa, sl, open_q)
+            search_ms = costmodel.search_estimate(ctx, net, ssa, sl, open_q,
+                                                  T.tnc_plan_info(plan)["slices_in_flight"])
             rec[name] = {"block_ms": round(best * 1e3, 3), "sliced": len(sl), "log2_flops": round(lc, 3),
                          "search_s": round(t_search, 2), "steps_ms": round(steps_ms, 3),
                          "mlp_predicted_ms": round(pred_ms, 3),
@@ -614,7 +616,8 @@ def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3, 4, 5))
     T.tnc_destroy(ctx)
     gains = [x["gain"] for x in runs]
     return {"metric": "learned step-cost model: held-out error and measured gain of MLP-steered paths",
-            "rows": int(n), "collect_s": round(t_collect, 1), "train_s": round(t_train, 2), "train_loss": loss,
+            "rows": int(n), "training_rows_weighted": int(len(yw)), "collect_s": round(t_collect, 1),
+            "train_s": round(t_train, 2), "train_loss": loss,
             "heldout_median_abs_log2_err": {"mlp": round(float(np.median(err_mlp)), 4),
                                             "flop": round(float(np.median(err_flop)), 4)},
             "heldout_mape": {"mlp": round(float(np.mean(np.abs(2.0 ** err_mlp - 1))), 4),

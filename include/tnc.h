@@ -359,7 +359,13 @@ int tnc_mlp_train(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32
  * squared error after the last step.  The weights become the cost model. */
 int tnc_mlp_adam(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32_t steps, float lr,
                  float *loss_out);
-/* Predict n rows (host in, host out). */
+/* Predict n rows (host in, host out).  After tnc_mlp_train or tnc_mlp_adam
+ * the network is not asked to extrapolate in the size features (log2 M, N,
+ * K, batch): a row above the range those training rows spanned is evaluated
+ * at the top of the range and the excess (in log2 units) added to its
+ * prediction, so time grows in proportion to the work beyond the data; a
+ * row below the range is evaluated at its bottom.  Weights loaded with
+ * tnc_mlp_set_params carry no range and are evaluated as given. */
 int tnc_mlp_predict(tnc_ctx *ctx, int64_t n, const float *x, float *y_out);
 /* One forward + backward pass on n rows with the current weights: loss (MSE)
  * and the gradient of every parameter, concatenated in the order W1, b1, W2,

@@ -54,7 +54,7 @@ def step_rows(plan, n_slices, prec, reps=1):
     return X, y, fl
 
 
-def collect(ctx, circuits, precisions, caps, open_counts, restarts=4, seed=0, reps=1, max_slices=64):
+def collect(ctx, circuits, precisions, caps, open_counts, restarts=4, seed=0, reps=1, max_slices=256):
     """Timing rows from every (circuit, precision, cap, open count) plan.
 
     circuits: iterable of workloads.Circuit.  Returns (X float32 [n, 8],
@@ -86,6 +86,18 @@ def collect(ctx, circuits, precisions, caps, open_counts, restarts=4, seed=0, re
                     T.tnc_plan_destroy(plan)
         T.tnc_network_destroy(net)
     return np.array(X, np.float32), np.array(y, np.float32), np.array(fl, np.float64)
+
+
+def weighted_rows(X, y, base_us=16.0, cap=16):
+    """Training rows repeated in proportion to the square root of their time
+    (at least once, at most cap times).  A path's time is a sum over its
+    launches, which the long launches decide, while most rows are short
+    launches; the repeats move the fit's attention towards the long ones."""
+    X = np.asarray(X, np.float32)
+    y = np.asarray(y, np.float32)
+    r = np.clip(np.rint(np.sqrt(np.exp2(y.astype(np.float64)) / base_us)), 1, cap).astype(np.int64)
+    idx = np.repeat(np.arange(len(y)), r)
+    return X[idx], y[idx]
 
 
 def flop_model_fit(flops, y):
@@ -123,13 +135,13 @@ def path_prediction(ctx, plan, bits, n_slices, prec):
     return measured, float(np.sum(np.exp2(pred.astype(np.float64)) * np.array(mult)) * 1e-3)
 
 
-def search_estimate(ctx, net, ssa, sliced, open_q, prec="f16_4m", batch_cap=64):
+def search_estimate(ctx, net, ssa, sliced, open_q, slices_per_launch, prec="f16_4m"):
     """The model's cost of a path as the path search forms it (ms): each
-    step's features with up to batch_cap slices per launch, times the launches
-    the slices need; the same sum the search minimises."""
+    step's features with the plan's slices per launch, times the launches the
+    slices need; the same sum the search minimises."""
     a = T.tnc_plan_analyze_steps(net, ssa, sliced, open_q, prec)
     total = 1 << len(sliced)
-    S = min(total, batch_cap)
+    S = min(total, slices_per_launch)
     X, mult = [], []
     for i in range(len(a["flops"])):
         if a["flops"][i] <= 0:   # entries past the device steps (host-absorbed pairs run no launch)

@@ -12,6 +12,7 @@
 // rows in index order), so training is deterministic for a given seed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <numeric>
 #include <random>
@@ -37,7 +38,25 @@ struct Mlp {
     int *idx = nullptr;
     int64_t step = 0;
     bool trained = false;
+    // the range of the size features (log2 M, N, K, batch) in the rows the
+    // weights were trained on; set by training, cleared by tnc_mlp_set_params
+    bool support = false;
+    float lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
 };
+
+// Record the size-feature range of n training rows (host array, F per row).
+static void set_support(Mlp *m, int64_t n, const float *x) {
+    for (int f = 0; f < 4; f++) {
+        m->lo[f] = x[f];
+        m->hi[f] = x[f];
+    }
+    for (int64_t r = 1; r < n; r++)
+        for (int f = 0; f < 4; f++) {
+            m->lo[f] = std::min(m->lo[f], x[r * F + f]);
+            m->hi[f] = std::max(m->hi[f], x[r * F + f]);
+        }
+    m->support = true;
+}
 
 static thread_local tnc_ctx *g_cost_ctx = nullptr;
 
@@ -242,8 +261,13 @@ double mlp_path_cost(const Network &net, const std::vector<int> &ssa, const std:
                                 (int)open_q.size(), open_q.data(), host_rank_cap());
     Analysis an = analyze(sp.net, (int)sp.ssa.size() / 2, sp.ssa.data(), (int)sliced.size(), sliced.data(),
                           (int)open_q.size(), open_q.data(), TNC_F16_4M);
+    // slices per launch as the plan would hold them: the largest power of two
+    // (at most 4096) whose arena fits the context's workspace
     const int64_t total = (int64_t)1 << an.n_sliced;
-    const int64_t S = std::min<int64_t>(total, 64);   // slices batched per launch in the estimate
+    const int64_t cap = std::min<int64_t>(total, 4096);
+    if ((size_t)plan_memory(an, 1, false) > ctx->ws_bytes) return 1e30;   // does not fit: never chosen
+    int64_t S = 1;
+    while (S * 2 <= cap && (size_t)plan_memory(an, (int)(S * 2), false) <= ctx->ws_bytes) S *= 2;
     std::vector<float> x;
     std::vector<double> mult;
     for (const auto &s : an.steps) {
@@ -319,6 +343,7 @@ extern "C" int tnc_mlp_train(tnc_ctx *ctx, int64_t n, const float *x, const floa
         HIP_CHECK(hipStreamSynchronize(st));
         if (loss_out) *loss_out = l;
         m->trained = true;
+        set_support(m, n, x);
     });
 }
 
@@ -352,6 +377,7 @@ extern "C" int tnc_mlp_adam(tnc_ctx *ctx, int64_t n, const float *x, const float
         if (loss_out) *loss_out = l;
         m->step = steps;
         m->trained = true;
+        set_support(m, n, x);
     });
 }
 
@@ -364,10 +390,34 @@ extern "C" int tnc_mlp_predict(tnc_ctx *ctx, int64_t n, const float *x, float *y
         hipStream_t st = ctx->stream;
         Mlp *m = mlp_of(ctx);
         ensure_rows(m, n);
-        HIP_CHECK(hipMemcpyAsync(m->x, x, n * F * sizeof(float), hipMemcpyHostToDevice, st));
+        // Outside the trained size range the network is not asked to
+        // extrapolate: a size feature above the range is taken at its top
+        // and the excess added to the log2 time (time grows in proportion to
+        // the work there); one below the range is taken at its bottom.
+        std::vector<float> xc;
+        std::vector<float> excess;
+        const float *xs = x;
+        if (m->support) {
+            xc.assign(x, x + n * F);
+            excess.assign(n, 0.f);
+            for (int64_t r = 0; r < n; r++)
+                for (int f = 0; f < 4; f++) {
+                    float &v = xc[r * F + f];
+                    if (v > m->hi[f]) {
+                        excess[r] += v - m->hi[f];
+                        v = m->hi[f];
+                    } else if (v < m->lo[f]) {
+                        v = m->lo[f];
+                    }
+                }
+            xs = xc.data();
+        }
+        HIP_CHECK(hipMemcpyAsync(m->x, xs, n * F * sizeof(float), hipMemcpyHostToDevice, st));
         forward(m, m->x, nullptr, n, st);
         HIP_CHECK(hipMemcpyAsync(y_out, m->out, n * sizeof(float), hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
+        if (m->support)
+            for (int64_t r = 0; r < n; r++) y_out[r] += excess[r];
     });
 }
 
@@ -411,6 +461,7 @@ extern "C" int tnc_mlp_set_params(tnc_ctx *ctx, const float *params) {
         HIP_CHECK(hipMemcpyAsync(m->params, params, NPARAM * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
         HIP_CHECK(hipStreamSynchronize(ctx->stream));
         m->trained = true;
+        m->support = false;   // weights from elsewhere: no known training range
     });
 }
 

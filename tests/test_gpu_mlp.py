@@ -6,8 +6,12 @@
 * Training is deterministic for a seed and reduces the loss.
 * Trained on the engine's own step timings, the MLP predicts held-out step
   times better than the FLOP model with a fitted scale.
-* Steering the path search with it gives a path whose measured time is not
-  worse than the FLOP-steered path (the gain is printed).
+* Outside the trained size range a prediction is the value at the range's
+  edge plus the excess (log2 time in proportion to the work).
+* Steering the path search with it (three seeds) gives paths whose measured
+  block times are at least as fast as the FLOP-steered ones, up to a 3% margin
+  for run-to-run timing spread (geometric-mean gain >= 0.97); the gains are
+  printed.
 """
 import time
 
@@ -105,6 +109,30 @@ def test_training_is_deterministic_and_learns(T, ctx):
     assert l1 < 0.02 * float(np.var(y)), (l1, float(np.var(y)))
 
 
+def test_prediction_outside_training_range(T, ctx):
+    x, y = _rows(1024, 4)   # size features log2 M, N, K in [0, 16], batch in [0, 8]
+    T.tnc_mlp_train(ctx, x, y, epochs=5, batch=128, lr=3e-3, seed=3)
+    base = x[:8].copy()
+    base[:, 3] = 8.0                      # at the top of the batch range
+    above = base.copy()
+    above[:, 3] = 11.0                    # 3 above it
+    above[:, 0] = 19.0                    # and M 3 above its top (16)
+    edge = base.copy()
+    edge[:, 0] = 16.0
+    below = edge.copy()
+    below[:, 2] = -4.0                    # K below its bottom (0): evaluated at 0
+    at0 = edge.copy()
+    at0[:, 2] = 0.0
+    p_edge, p_above = T.tnc_mlp_predict(ctx, edge), T.tnc_mlp_predict(ctx, above)
+    np.testing.assert_allclose(p_above - p_edge, 6.0, rtol=0, atol=1e-5)
+    np.testing.assert_array_equal(T.tnc_mlp_predict(ctx, below), T.tnc_mlp_predict(ctx, at0))
+    # weights set from outside carry no range: evaluated as given
+    T.tnc_mlp_set_params(ctx, T.tnc_mlp_get_params(ctx))
+    p_raw = T.tnc_mlp_predict(ctx, above)
+    ref, _ = omlp.forward(T.tnc_mlp_get_params(ctx).astype(np.float64), above.astype(np.float64))
+    np.testing.assert_allclose(p_raw, ref, rtol=1e-5, atol=1e-4)
+
+
 def _timing_data(T, ctx):
     from paper_2407_00769_amd import costmodel
     circs = []
@@ -128,7 +156,8 @@ def test_mlp_beats_flop_model_and_steers_search(T, ctx):
     perm = rng.permutation(n)
     tr, te = perm[: int(0.8 * n)], perm[int(0.8 * n):]
     t0 = time.perf_counter()
-    loss = T.tnc_mlp_train(ctx, X[tr], y[tr], epochs=60, batch=256, lr=2e-3, seed=7)
+    Xw, yw = costmodel.weighted_rows(X[tr], y[tr])
+    loss = T.tnc_mlp_train(ctx, Xw, yw, epochs=40, batch=256, lr=2e-3, seed=7)
     t_train = time.perf_counter() - t0
     pred = T.tnc_mlp_predict(ctx, X[te])
     c = costmodel.flop_model_fit(fl[tr], y[tr])
@@ -138,7 +167,8 @@ def test_mlp_beats_flop_model_and_steers_search(T, ctx):
     print(f"\nrows {n} (collect {t_collect:.1f} s, train {t_train:.1f} s, loss {loss:.4f}); held-out median "
           f"|log2 error|: MLP {err_mlp:.3f}, FLOP model {err_flop:.3f}")
     assert err_mlp < err_flop
-    # steer the search for the 30-qubit circuit and time both choices
+    # steer the search for the 30-qubit circuit under each model (three seeds)
+    # and time both choices: best of 3 executes each
     T.tnc_costmodel_use(ctx)
     c30 = workloads.config_circuit(2)
     st = workloads.tn_structure(c30)
@@ -146,21 +176,23 @@ def test_mlp_beats_flop_model_and_steers_search(T, ctx):
     net = T.tnc_network_create(r, l, d, c30.n_qubits, o)
     open_q = list(range(20, 30))
     bits = workloads.prefix_bitstrings(30, open_q, 1024, 3)
-    times = {}
-    for model in (0, 1):
-        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 22, cost_model=model, restarts=32, seed=1)
-        plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
-        nsl = 1 << len(sl)
-        T.tnc_execute(plan, bits, 0, nsl)
-        best = 1e9
-        for _ in range(3):
-            _, rep = T.tnc_execute(plan, bits, 0, nsl)
-            best = min(best, rep["seconds"])
-        times[model] = best
-        T.tnc_plan_destroy(plan)
+    gains = []
+    for seed in (1, 2, 3):
+        times = {}
+        for model in (0, 1):
+            ssa, sl, _ = T.tnc_search(net, len(r), open_q, 22, cost_model=model, restarts=32, seed=seed)
+            plan = T.tnc_plan_create(ctx, net, ssa, sl, open_q, "f16_4m")
+            nsl = 1 << len(sl)
+            T.tnc_execute(plan, bits, 0, nsl)
+            times[model] = min(T.tnc_execute(plan, bits, 0, nsl)[1]["seconds"] for _ in range(3))
+            T.tnc_plan_destroy(plan)
+        gains.append(times[0] / times[1])
+        print(f"seed {seed}: FLOP-steered {times[0] * 1e3:.2f} ms, MLP-steered {times[1] * 1e3:.2f} ms, "
+              f"gain x{gains[-1]:.3f}")
     T.tnc_costmodel_use(None)
     T.tnc_network_destroy(net)
-    gain = times[0] / times[1]
-    print(f"30-qubit block: FLOP-steered {times[0] * 1e3:.2f} ms, MLP-steered {times[1] * 1e3:.2f} ms, "
-          f"gain x{gain:.3f}")
-    assert times[1] <= 1.10 * times[0]
+    geo = float(np.exp(np.mean(np.log(gains))))
+    print(f"geometric-mean gain x{geo:.3f}")
+    # the learned model must not lose to the FLOP model: a 3% margin covers
+    # the run-to-run spread of the block times
+    assert geo >= 0.97, gains
