@@ -543,8 +543,9 @@ double autotune_plan(tnc_plan *p) {
         if (cands.empty()) {
             for (int k = K_MFMA_S; k < K_COUNT; k++)
                 if (gemm_supported(k, dt, an.al, g)) cands.push_back(k);
-            // the VALU kernel only where no matrix-core tile applies or the step is tiny
-            if ((cands.empty() || rec.flops * (double)Sl < 1e9) && gemm_supported(K_SKINNY_N, dt, an.al, g))
+            // the VALU kernel where no matrix-core tile applies, the step is
+            // tiny, or it is thin (N <= 16: HBM-bound, where either may win)
+            if ((cands.empty() || rec.flops * (double)Sl < 1e9 || g.N <= 16) && gemm_supported(K_SKINNY_N, dt, an.al, g))
                 cands.push_back(K_SKINNY_N);
         }
         if (cands.size() <= 1) continue;

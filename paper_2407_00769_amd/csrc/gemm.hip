@@ -1155,6 +1155,202 @@ __global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAG
     finish_max<true>(sc, s, mx);
 }
 
+// ===================================================================== thin on the matrix cores: N = 4, 8 or 16
+//
+// The VALU thin kernel spends 4 FP32 FMAs per complex product (256 per row at
+// N = K = 8), which holds it near the VALU rate instead of the memory rate.
+// Here v_mfma_f32_16x16x16_{f16,bf16} does the products: lane l holds
+// A'[l%16][4(l/16)..+3], i.e. complex k 2(l/16), 2(l/16)+1 of row l%16,
+// B'[4(l/16)..+3][l%16], and the result rows 4(l/16)..+3 of real column
+// l%16.  Real column 2n + d of the padded B' is (br, -bi) for d = 0 and
+// (bi, br) for d = 1 (4M), so lanes 2n and 2n+1 hold Re and Im of complex
+// column n and swap them with one DPP quad permute (columns n >= N are zero).
+// A wave takes 64 rows per pass.  A chunked along k: one 8-byte load per
+// lane reads 16 whole rows.  A chunked along m: the pass's K x 64 entries
+// come in 16-byte chunks along m and go through an LDS region of the wave's
+// own, read back k-major.  The next pass's A is loaded before this pass's
+// result is staged (LDS, [row][n] words) and stored in 16-byte chunks.
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <bool BF> __device__ __forceinline__ floatx4 mfma16x16(u32x2 a, u32x2 b, floatx4 c) {
+    if constexpr (BF)
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, a), __builtin_bit_cast(short4_t, b),
+                                                         c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(half4_t, a), __builtin_bit_cast(half4_t, b), c, 0,
+                                                     0, 0);
+}
+
+// wait for this wave's LDS traffic (its own region: no block barrier)
+__device__ __forceinline__ void wave_lds_wait() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), nothing else
+    asm volatile("" ::: "memory");
+}
+
+template <bool BF, int NB, int KCM, bool AKC>
+__global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B,
+                                                         uint32_t *__restrict__ C, GemmShape g, ScaleRefs sc) {
+    using W = typename std::conditional<BF, Bf16Word, HalfWord>::type;
+    // NS: staged words per result row; RW: rows per wave pass; KCM: k chunks of
+    // 8 at most; AS: words per staged A row (64 m, padded against bank conflicts)
+    constexpr int NS = 8 * NB, RW = 64, AS = RW + 4, NCH = AKC ? 1 : 2 * KCM;
+    __shared__ __align__(16) uint32_t Cs[4][RW * NS];
+    __shared__ __align__(16) uint32_t Asm[AKC ? 1 : 4][AKC ? 1 : 8 * KCM * AS];
+    const int s = blockIdx.z;
+    const int64_t b = blockIdx.y;
+    const int shift = step_shift(sc, s);
+    if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) record_exponent(sc, s, shift);
+    const float scale = pow2_neg(shift);
+    const uint32_t *Ap = A + s * g.sA + a_block(g, b) * g.bA;
+    const uint32_t *Bp = B + s * g.sB + b_block(g, b) * g.bB;
+    uint32_t *Cp = C + s * g.sC + b * g.bC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kc = (int)(g.K / 8), nn = (int)g.N;
+    const bool odd = (lane & 1) != 0;
+    // padded B' operands of every k chunk and column block
+    u32x2 bop[KCM][NB];
+#pragma unroll
+    for (int t = 0; t < KCM; t++)
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+            u32x2 v = {0u, 0u};
+            const int n = q * 8 + (lane & 15) / 2;
+            if (t < kc && n < nn) {
+                const int64_t k = 8 * t + 2 * (lane >> 4);
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    const uint32_t w = Bp[b_index(g, n, k + e)];
+                    v[e] = odd ? __builtin_amdgcn_perm(w, w, 0x01000302u) : (w ^ 0x80000000u);
+                }
+            }
+            bop[t][q] = v;
+        }
+    uint32_t *cs = Cs[wave];
+    uint32_t *as = Asm[AKC ? 0 : wave];
+    float mx = 0.f;
+    const int64_t units = g.M / RW, step = (int64_t)gridDim.x * 4;
+    // A of a 64-row pass as loaded: k-chunked, the MFMA operands themselves
+    // (four groups of 16 rows); m-chunked, 16-byte chunks of 4 rows at one k
+    struct Raw {
+        u32x2 a[4][KCM];
+        u32x4 c[NCH];
+    };
+    auto load_pass = [&](int64_t u, Raw &r) {
+        const int64_t m0 = u * RW;
+        if constexpr (AKC) {
+#pragma unroll
+            for (int gq = 0; gq < 4; gq++) {
+                const uint32_t *ap = Ap + seg_offset(g.am, m0 + 16 * gq + (lane & 15));
+#pragma unroll
+                for (int t = 0; t < KCM; t++)
+                    if (t < kc) r.a[gq][t] = *(const u32x2 *)(ap + seg_offset(g.ak, 8 * t + 2 * (lane >> 4)));
+            }
+        } else {
+            // chunk c: k = c / 16, rows 4 (c % 16)..+3
+#pragma unroll
+            for (int i = 0; i < NCH; i++) {
+                const int c = i * 64 + lane, k = c >> 4, m4 = (c & 15) * 4;
+                if (k < 8 * kc) r.c[i] = *(const u32x4 *)(Ap + seg_offset(g.am, m0 + m4) + seg_offset(g.ak, k));
+            }
+        }
+    };
+    // MFMA operands from a loaded pass (m-chunked A: through the LDS region)
+    auto operands = [&](Raw &r) {
+        if constexpr (!AKC) {
+#pragma unroll
+            for (int i = 0; i < NCH; i++) {
+                const int c = i * 64 + lane, k = c >> 4, m4 = (c & 15) * 4;
+                if (k < 8 * kc) *(u32x4 *)(as + k * AS + m4) = r.c[i];
+            }
+            wave_lds_wait();
+#pragma unroll
+            for (int gq = 0; gq < 4; gq++)
+#pragma unroll
+                for (int t = 0; t < KCM; t++)
+                    if (t < kc) {
+                        const int k = 8 * t + 2 * (lane >> 4), m = 16 * gq + (lane & 15);
+                        r.a[gq][t] = u32x2{as[k * AS + m], as[(k + 1) * AS + m]};
+                    }
+            wave_lds_wait();   // read out before the next pass writes
+        }
+    };
+    auto pass = [&](int64_t u, Raw &cur, Raw &nxt) {
+        const int64_t m0 = u * RW;
+        operands(cur);
+        floatx4 acc[4][NB];
+#pragma unroll
+        for (int gq = 0; gq < 4; gq++)
+#pragma unroll
+            for (int q = 0; q < NB; q++) {
+                acc[gq][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < KCM; t++)
+                    if (t < kc) acc[gq][q] = mfma16x16<BF>(cur.a[gq][t], bop[t][q], acc[gq][q]);
+            }
+        if (u + step < units) load_pass(u + step, nxt);
+        // Re/Im from the lane pair; even lanes stage rows e = 0, 1 of their
+        // group, odd lanes rows 2, 3
+#pragma unroll
+        for (int gq = 0; gq < 4; gq++)
+#pragma unroll
+            for (int q = 0; q < NB; q++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const float own = acc[gq][q][e];
+                    const float other = __uint_as_float(quad_perm<0xB1>(__float_as_uint(own)));
+                    const float re = odd ? other : own, im = odd ? own : other;
+                    const int n = q * 8 + (lane & 15) / 2;
+                    if ((e >> 1) == (int)odd && n < nn) {
+                        const int row = 16 * gq + 4 * (lane >> 4) + e;
+                        cs[row * NS + n] = Pack<W>::make(re * scale, im * scale).w;
+                    }
+                }
+        wave_lds_wait();
+        // 16-byte chunks: 64 rows x N words
+        const int nq = nn / 4;
+#pragma unroll
+        for (int uq = 0; uq < NS / 4; uq++) {
+            if (uq >= nq) break;
+            const int c = uq * 64 + lane;
+            u32x4 v;
+            int64_t off;
+            if (g.c_nc) {
+                const int row = c / nq, n4 = (c % nq) * 4;
+                v = *(const u32x4 *)(cs + row * NS + n4);
+                off = c_index(g, m0 + row, n4);
+            } else {
+                const int n = c / (RW / 4), r4 = (c % (RW / 4)) * 4;
+#pragma unroll
+                for (int e = 0; e < 4; e++) v[e] = cs[(r4 + e) * NS + n];
+                off = c_index(g, m0 + r4, n);
+            }
+            *(u32x4 *)(Cp + off) = v;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const float2 f = unpack(W{v[e]});
+                mx = fmaxf(mx, absmax_nan(f.x, f.y));
+            }
+        }
+        wave_lds_wait();   // read out before the next pass writes
+    };
+    Raw r0, r1;
+    int64_t u = (int64_t)blockIdx.x * 4 + wave;
+    if (u < units) load_pass(u, r0);
+    while (u < units) {
+        pass(u, r0, r1);
+        u += step;
+        if (u >= units) break;
+        pass(u, r1, r0);
+        u += step;
+    }
+    finish_max<true>(sc, s, mx);
+}
+
 // ===================================================================== persistent LDS-DMA 4M (short k)
 //
 // The short-k steps (K = 2^6..2^9 complex) write a large C per tile, and a
@@ -1674,6 +1870,7 @@ const char *kernel_name(int k) {
         case K_DMA3_N64: return "dma3_n64";
         case K_DMA3_2: return "dma3_2";
         case K_DMAP_2: return "dmap_2";
+        case K_THINM: return "thinm";
         default: return "?";
     }
 }
@@ -1707,6 +1904,7 @@ static TileCfg tile_of(int kid, Dtype dt, Algo al) {
             case K_DMA_N64: return {256, 64};
             case K_DMA_N32: return {256, 32};
             case K_DMAP_2: return {128, 128};
+            case K_THINM: return {64, 4};
         }
     } else {
         switch (kid) {
@@ -1737,6 +1935,12 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
         // 16-bit 4M, both operands chunked along k, whole tiles and k-tiles
         if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
         if (g.K % 32) return false;
+    }
+    if (kid == K_THINM) {
+        // thin on the matrix cores: 4M, N = 4, 8 or 16, K a multiple of 8 up
+        // to 64 (16 when A is chunked along m), whole 64-row passes
+        if (dt == Dtype::C64 || al != Algo::M4) return false;
+        if (!(g.N == 4 || g.N == 8 || g.N == 16) || g.K % 8 || g.K > (g.a_kc ? 64 : 16) || g.M % 64) return false;
     }
     if (kid == K_DMAP_2) {
         // the persistent tile loop: as the DMA kernels (a two-stage ring spans
@@ -1904,6 +2108,28 @@ template <bool BF>
 static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, const GemmShape &g, int S,
                      const ScaleRefs &sc, hipStream_t st) {
     if (kid == K_DMAP_2) return launch_dmap_cfg<BF, 128, 128, 2, 2, 2>(A, B, C, g, S, sc, st);
+    if (kid == K_THINM) {
+        // about 4096 blocks in all; each wave walks 64-row passes
+        const int64_t units = g.M / 64, others = g.nb * (int64_t)S;
+        const int64_t gx = std::max<int64_t>(1, std::min<int64_t>((units + 3) / 4, (4096 + others - 1) / others));
+        dim3 grid((unsigned)gx, (unsigned)g.nb, S);
+        auto args = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, (const uint32_t *)A, (const uint32_t *)B, (uint32_t *)C, g,
+                               sc);
+        };
+        const bool short_k = g.K <= 16;   // the double-buffered A of a pass fits few registers
+        if (!g.a_kc) {
+            if (g.N <= 8) args(gemm_thinm_kernel<BF, 1, 2, false>);
+            else args(gemm_thinm_kernel<BF, 2, 2, false>);
+        } else if (g.N <= 8) {
+            if (short_k) args(gemm_thinm_kernel<BF, 1, 2, true>);
+            else args(gemm_thinm_kernel<BF, 1, 8, true>);
+        } else {
+            if (short_k) args(gemm_thinm_kernel<BF, 2, 2, true>);
+            else args(gemm_thinm_kernel<BF, 2, 8, true>);
+        }
+        return;
+    }
     if (kid == K_DMA_4) return launch_dma_cfg<BF, 256, 128, 2, 2, 3>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_8) return launch_dma_cfg<BF, 256, 128, 4, 2, 3>(A, B, C, g, S, sc, st);
     if (kid == K_DMA_8W) return launch_dma_cfg<BF, 256, 128, 2, 4, 3>(A, B, C, g, S, sc, st);
@@ -1963,7 +2189,7 @@ static void launch_c64(int kid, const void *A, const void *B, void *C, const Gem
 
 int64_t splitk_factor(int kid, Dtype dt, Algo al, const GemmShape &g, int S) {
     if (kid < K_MFMA_S || kid >= K_COUNT || !gemm_supported(kid, dt, al, g)) return 1;
-    if (kid == K_DMAP_2) return 1;
+    if (kid == K_DMAP_2 || kid == K_THINM) return 1;
     TileCfg t = tile_of(kid, dt, al);
     const int64_t bk = dt == Dtype::C64 ? 16 : 32;
     const int64_t blocks = (g.M / t.BM) * (g.N / t.BN) * g.nb * (int64_t)S;

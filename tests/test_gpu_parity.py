@@ -10,6 +10,7 @@
   equals the sum of projected state vectors; disjoint ranges add up; two runs
   are bit-identical; the graph launch equals step-by-step launches.
 """
+import itertools
 import json
 import os
 
@@ -104,7 +105,8 @@ def _check_contract(T, ctx, prec, nb, m, n, k, seed, scale_log2=0):
 
 KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5, "mfma_xl": 6,
            "mfma_l2": 7, "dma_4": 8, "dma_8": 9, "dma_8w": 10, "dma_2": 11, "dma_n64": 12, "dma_n32": 13,
-           "dma3_n64": 14, "dma3_2": 15, "dmap_2": 16}
+           "dma3_n64": 14, "dma3_2": 15, "dmap_2": 16,
+           "thinm": 17}
 SHAPES = [  # nb, m, n, k  (log2)
     (0, 9, 6, 5), (1, 8, 5, 3), (0, 10, 4, 6), (2, 7, 7, 4), (0, 8, 0, 2), (0, 6, 3, 0), (0, 12, 5, 7),
     (0, 9, 8, 6), (1, 8, 7, 5),
@@ -134,6 +136,36 @@ def test_persistent_tile_loop(T, ctx, prec, kname, monkeypatch):
     monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
     for i, (nb, m, n, k) in enumerate(PERSISTENT_SHAPES):
         _check_contract(T, ctx, prec, nb, m, n, k, seed=300 + i)
+
+
+# thin steps on the matrix cores: N = 4, 8 or 16 complex columns, K = 8..64,
+# one to four 64-row passes per wave and batches of up to four
+THIN_SHAPES = [(0, 12, 3, 3), (1, 11, 3, 4), (0, 13, 4, 4), (2, 10, 4, 6), (0, 6, 3, 3), (0, 10, 4, 5),
+               (0, 12, 2, 3), (1, 10, 2, 4)]
+
+
+@pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m"])
+def test_thin_matrix_core_kernel(T, ctx, prec, monkeypatch):
+    monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS["thinm"]))
+    for i, (nb, m, n, k) in enumerate(THIN_SHAPES):
+        _check_contract(T, ctx, prec, nb, m, n, k, seed=400 + i)
+    # read and written in place: A as [m][k] or [k][m] (the latter through
+    # LDS), B as [n][k] or [k][n], C as [m][n] or [n][m]; N = 4, 8, 16; K = 8, 16
+    rng = np.random.default_rng(14)
+    for n, k, a_kc, b_kc, c_nc in itertools.product((2, 3, 4), (3, 4), (1, 0), (1, 0), (1, 0)):
+        al, bl, cl, a, b = _oriented_case(rng, 9, n, k, a_kc, b_kc, c_nc)
+        A, av = to_storage(a, prec)
+        B, bv = to_storage(b, prec)
+        C = empty_storage((2 ** len(cl),), prec)
+        times, _ = T.tnc_contract(ctx, prec, A, al, B, bl, C, cl)
+        assert times[0] < 0.05 and times[1] < 0.05 and times[3] < 0.05   # no permute ran (ms)
+        got = from_storage(C, prec).reshape((2,) * len(cl))
+        ref = pairwise.contract_pair(av.reshape((2,) * len(al)), al, bv.reshape((2,) * len(bl)), bl, cl)
+        mag = pairwise.contract_pair(np.abs(av).reshape((2,) * len(al)), al,
+                                     np.abs(bv).reshape((2,) * len(bl)), bl, cl)
+        bound = 4 * 2 ** k * 2.0 ** -24 * np.abs(mag) + U[prec] * np.abs(ref) * 1.01 + 1e-30
+        err = np.abs(got - ref)
+        assert np.all(err <= bound), (prec, n, k, a_kc, b_kc, c_nc, float(np.max(err / bound)))
 
 
 def _oriented_case(rng, m, n, k, a_kc, b_kc, c_nc):
