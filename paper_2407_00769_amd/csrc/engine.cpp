@@ -570,36 +570,53 @@ double autotune_plan(tnc_plan *p) {
             launch_fill_random(dt, (void *)pa, wa, 0x5eed0000u + (uint32_t)rec.a, st);
             launch_fill_random(dt, (void *)pb, wb, 0x5eed8000u + (uint32_t)rec.b, st);
         }
-        // The clock of a loaded GPU drifts by several percent between
-        // launches, so big steps are timed in two rounds over the candidates
-        // (the second only for those within 25% of the best) and each keeps
-        // its fastest time.
-        std::vector<double> t_ms(cands.size(), 1e30);
+        // The clock of a loaded MI355X follows the power its matrix cores
+        // draw, so a candidate timed after a cooler stretch looks faster.  A
+        // big step first heats the chip (at least 100 ms of the first
+        // candidate), then is timed in three rounds (forward, backward,
+        // forward order over the candidates; after the first round only
+        // those within 20% of the best), and each candidate is scored by the
+        // median of its times.
+        auto time_one = [&](int k, int reps) {
+            HIP_CHECK(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; r++)
+                launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
+            HIP_CHECK(hipEventRecord(e1, st));
+            HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms / reps;
+        };
+        std::vector<std::vector<double>> t_ms(cands.size());
         double best = 1e30;
-        const int rounds = big ? 2 : 1;
+        const int rounds = big ? 3 : 1;
+        const int reps = big ? 1 : 2;
+        if (big) {
+            double heat = 0;
+            for (int w = 0; w < 8 && heat < 100.0; w++) heat += time_one(cands[0], 1);
+        }
         for (int rd = 0; rd < rounds; rd++) {
-            for (size_t ci = 0; ci < cands.size(); ci++) {
+            for (size_t i = 0; i < cands.size(); i++) {
+                const size_t ci = (rd % 2 == 0) ? i : cands.size() - 1 - i;
                 const int k = cands[ci];
-                if (rd > 0 && t_ms[ci] > 1.25 * best) continue;
+                if (rd > 0 && *std::min_element(t_ms[ci].begin(), t_ms[ci].end()) > 1.2 * best) continue;
                 if (rd == 0) launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);   // warm
-                HIP_CHECK(hipEventRecord(e0, st));
-                const int reps = big ? 1 : 2;
-                for (int r = 0; r < reps; r++)
-                    launch_gemm(k, dt, an.al, pa, pb, pc, g, Sl, dt != Dtype::C64 ? &sc : nullptr, st);
-                HIP_CHECK(hipEventRecord(e1, st));
-                HIP_CHECK(hipEventSynchronize(e1));
-                float ms = 0;
-                HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                t_ms[ci] = std::min(t_ms[ci], (double)ms / reps);
-                best = std::min(best, t_ms[ci]);
+                const double ms = time_one(k, reps);
+                t_ms[ci].push_back(ms);
+                best = std::min(best, ms);
             }
         }
         int best_k = rec.kernel;
-        for (size_t ci = 0; ci < cands.size(); ci++)
-            if (t_ms[ci] == best) {
+        double best_score = 1e30;
+        for (size_t ci = 0; ci < cands.size(); ci++) {
+            std::vector<double> v = t_ms[ci];
+            std::sort(v.begin(), v.end());
+            const double med = v.size() % 2 ? v[v.size() / 2] : 0.5 * (v[v.size() / 2 - 1] + v[v.size() / 2]);
+            if (med < best_score) {
+                best_score = med;
                 best_k = cands[ci];
-                break;
             }
+        }
         rec.kernel = best_k;
         g_tune[key] = best_k;
         tune_cache_append(key, best_k);
