@@ -455,6 +455,15 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         // permute costs at most a thousandth of the large operand's bytes; on
         // the 53-qubit path it removes a quarter of the permute traffic.
         if (ob >= 0 && ((B.rank() <= 8 && A.rank() >= 16) || B.rank() + 10 <= A.rank())) ob = -1;
+        // A kept operand at most 1/64 of the result is permuted into the
+        // ranked order as well: the result's labels then follow the order in
+        // which its consumers sum them rather than the operand's producers'
+        // order, which can force a permute of the much larger result later
+        // (on the 53-qubit path a 2^32-entry tensor, a third of that path's
+        // permute traffic).  The permute costs at most 1/32 of the result's
+        // bytes.
+        if (oa >= 0 && A.rank() + 6 <= Z.rank()) oa = -1;
+        if (ob >= 0 && B.rank() + 6 <= Z.rank()) ob = -1;
         // On a compute-bound 16-bit 4M step the k-chunked kernels (operands
         // streamed into LDS as whole k rows) are several times faster than
         // the ones that transpose in registers: permute an operand that is
