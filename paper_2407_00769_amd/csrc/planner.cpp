@@ -476,106 +476,129 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             if (ob == 0 && cheap(B)) ob = -1;
         }
         const double szA = std::ldexp(1.0, A.rank()), szB = std::ldexp(1.0, B.rank());
-        // batch and k orders must agree between A and B; take them from a kept
-        // operand, preferring the larger
-        std::vector<int> beta_o, k_o;
-        bool keepA = oa >= 0, keepB = ob >= 0;
-        if (keepA && keepB) {
-            if (extract(A.labels, grp, 0) != extract(B.labels, grp, 0) ||
-                extract(A.labels, grp, 2) != extract(B.labels, grp, 2)) {
-                if (szA >= szB) keepB = false;
-                else keepA = false;
-            }
-        }
-        if (keepA) {
-            beta_o = extract(A.labels, grp, 0);
-            k_o = extract(A.labels, grp, 2);
-        } else if (keepB) {
-            beta_o = extract(B.labels, grp, 0);
-            k_o = extract(B.labels, grp, 2);
-        } else {
-            const TensorRec &src = (!A.leaf || B.leaf) ? A : B;
-            beta_o = extract(src.labels, grp, 0);
-            k_o = extract(src.labels, grp, 2);
-        }
-        std::vector<int> m_o = extract(A.labels, grp, 1), n_o = extract(B.labels, grp, 1);
-        // Result order.  Free orders of operands that are permuted or gathered
-        // follow the consumer's groups; within a group, labels summed later sit
-        // higher, so the stem keeps its soon-summed labels at the low end.
-        auto ranked = [&](std::vector<int> v, bool kfirst) {
-            std::stable_sort(v.begin(), v.end(), [&](int p, int q) {
-                auto key = [&](int l) { return cg[l] == 0 ? 0 : (kfirst ? (cg[l] == 2 ? 1 : 2) : cg[l]); };
-                if (key(p) != key(q)) return key(p) < key(q);
-                return kstep[p] > kstep[q];
-            });
-            return v;
-        };
-        // score of a result order: -1 if the consumer must permute it, else the
-        // shorter of the writer's and the reader's lowest runs (capped at 5
-        // bits: 128-byte runs coalesce fully), minus a small cost per split
-        std::vector<int> gw(L, -1);
-        auto score = [&](const std::vector<int> &zo, const std::vector<int> &mm, int nsplit) -> double {
-            for (int l : zo) gw[l] = 2;
-            for (int l : mm) gw[l] = 1;
-            for (int l : beta_o) gw[l] = 0;
-            int lgw = 0;
-            int wlow = inplace(zo, gw, lgw);
-            for (int l : zo) gw[l] = -1;
-            if (!wlow) return -1;
-            int rlow = 5;
-            if (Z.consumer >= 0) {
-                int lgr = 0;
-                rlow = inplace(zo, cg, lgr);
-                if (!rlow) return -1;
-            }
-            return std::min({wlow, rlow, 5}) - 0.25 * nsplit;
-        };
+        std::vector<int> beta_o, k_o, m_o, n_o, best_z;
         auto cat3 = [](const std::vector<int> &a, const std::vector<int> &b, const std::vector<int> &c) {
             std::vector<int> r = a;
             r.insert(r.end(), b.begin(), b.end());
             r.insert(r.end(), c.begin(), c.end());
             return r;
         };
-        std::vector<int> best_m = keepA ? m_o : ranked(m_o, false), best_n = keepB ? n_o : ranked(n_o, false);
-        std::vector<int> best_z;
-        double best_s = -2;
-        for (int kfirst = 0; kfirst < 2; kfirst++) {
-            std::vector<int> mm = keepA ? m_o : ranked(m_o, kfirst), nn = keepB ? n_o : ranked(n_o, kfirst);
-            // plain [batch][X][Y] first; split layouts [batch][Xh][Yh][Xl][Yl]
-            // only if no plain order fits with runs of at least 4 entries
-            for (int pass = 0; pass < 2 && best_s < 2.5; pass++) {
-                for (int xm = 1; xm >= 0; xm--) {
-                    const auto &X = xm ? mm : nn;
-                    const auto &Y = xm ? nn : mm;
-                    const int nx = (int)X.size(), ny = (int)Y.size();
-                    for (int sx = pass ? 0 : nx; sx <= nx; sx++)
-                        for (int sy = pass ? 0 : ny; sy <= ny; sy++) {
-                            int nsplit = (sx > 0 && sx < nx) + (sy > 0 && sy < ny);
-                            if (pass && !nsplit) continue;
-                            std::vector<int> zo = beta_o;
-                            zo.insert(zo.end(), X.begin(), X.begin() + sx);
-                            zo.insert(zo.end(), Y.begin(), Y.begin() + sy);
-                            zo.insert(zo.end(), X.begin() + sx, X.end());
-                            zo.insert(zo.end(), Y.begin() + sy, Y.end());
-                            double sc = score(zo, mm, nsplit);
-                            if (sc > best_s) {
-                                best_s = sc;
-                                best_z = zo;
-                                best_m = mm;
-                                best_n = nn;
-                            }
-                        }
+        bool keepA = false, keepB = false;
+        // A kept operand smaller than the result that leaves the result in no
+        // order its consumer can read in place is permuted into the ranked
+        // order instead, if that lets the result be read in place: the
+        // operand's permute is cheaper than the consumer's permute of the
+        // larger result.  Failing that, the first choice stands.
+        bool dropA = false, dropB = false;
+        for (int attempt = 0; attempt < 3; attempt++) {
+            keepA = oa >= 0 && !dropA;
+            keepB = ob >= 0 && !dropB;
+            beta_o.clear();
+            k_o.clear();
+            // batch and k orders must agree between A and B; take them from a kept
+            // operand, preferring the larger
+            if (keepA && keepB) {
+                if (extract(A.labels, grp, 0) != extract(B.labels, grp, 0) ||
+                    extract(A.labels, grp, 2) != extract(B.labels, grp, 2)) {
+                    if (szA >= szB) keepB = false;
+                    else keepA = false;
                 }
             }
-            if (best_s >= 0) break;
+            if (keepA) {
+                beta_o = extract(A.labels, grp, 0);
+                k_o = extract(A.labels, grp, 2);
+            } else if (keepB) {
+                beta_o = extract(B.labels, grp, 0);
+                k_o = extract(B.labels, grp, 2);
+            } else {
+                const TensorRec &src = (!A.leaf || B.leaf) ? A : B;
+                beta_o = extract(src.labels, grp, 0);
+                k_o = extract(src.labels, grp, 2);
+            }
+            m_o = extract(A.labels, grp, 1);
+            n_o = extract(B.labels, grp, 1);
+            // Result order.  Free orders of operands that are permuted or gathered
+            // follow the consumer's groups; within a group, labels summed later sit
+            // higher, so the stem keeps its soon-summed labels at the low end.
+            auto ranked = [&](std::vector<int> v, bool kfirst) {
+                std::stable_sort(v.begin(), v.end(), [&](int p, int q) {
+                    auto key = [&](int l) { return cg[l] == 0 ? 0 : (kfirst ? (cg[l] == 2 ? 1 : 2) : cg[l]); };
+                    if (key(p) != key(q)) return key(p) < key(q);
+                    return kstep[p] > kstep[q];
+                });
+                return v;
+            };
+            // score of a result order: -1 if the consumer must permute it, else the
+            // shorter of the writer's and the reader's lowest runs (capped at 5
+            // bits: 128-byte runs coalesce fully), minus a small cost per split
+            std::vector<int> gw(L, -1);
+            auto score = [&](const std::vector<int> &zo, const std::vector<int> &mm, int nsplit) -> double {
+                for (int l : zo) gw[l] = 2;
+                for (int l : mm) gw[l] = 1;
+                for (int l : beta_o) gw[l] = 0;
+                int lgw = 0;
+                int wlow = inplace(zo, gw, lgw);
+                for (int l : zo) gw[l] = -1;
+                if (!wlow) return -1;
+                int rlow = 5;
+                if (Z.consumer >= 0) {
+                    int lgr = 0;
+                    rlow = inplace(zo, cg, lgr);
+                    if (!rlow) return -1;
+                }
+                return std::min({wlow, rlow, 5}) - 0.25 * nsplit;
+            };
+            std::vector<int> best_m = keepA ? m_o : ranked(m_o, false), best_n = keepB ? n_o : ranked(n_o, false);
+            best_z.clear();
+            double best_s = -2;
+            for (int kfirst = 0; kfirst < 2; kfirst++) {
+                std::vector<int> mm = keepA ? m_o : ranked(m_o, kfirst), nn = keepB ? n_o : ranked(n_o, kfirst);
+                // plain [batch][X][Y] first; split layouts [batch][Xh][Yh][Xl][Yl]
+                // only if no plain order fits with runs of at least 4 entries
+                for (int pass = 0; pass < 2 && best_s < 2.5; pass++) {
+                    for (int xm = 1; xm >= 0; xm--) {
+                        const auto &X = xm ? mm : nn;
+                        const auto &Y = xm ? nn : mm;
+                        const int nx = (int)X.size(), ny = (int)Y.size();
+                        for (int sx = pass ? 0 : nx; sx <= nx; sx++)
+                            for (int sy = pass ? 0 : ny; sy <= ny; sy++) {
+                                int nsplit = (sx > 0 && sx < nx) + (sy > 0 && sy < ny);
+                                if (pass && !nsplit) continue;
+                                std::vector<int> zo = beta_o;
+                                zo.insert(zo.end(), X.begin(), X.begin() + sx);
+                                zo.insert(zo.end(), Y.begin(), Y.begin() + sy);
+                                zo.insert(zo.end(), X.begin() + sx, X.end());
+                                zo.insert(zo.end(), Y.begin() + sy, Y.end());
+                                double sc = score(zo, mm, nsplit);
+                                if (sc > best_s) {
+                                    best_s = sc;
+                                    best_z = zo;
+                                    best_m = mm;
+                                    best_n = nn;
+                                }
+                            }
+                    }
+                }
+                if (best_s >= 0) break;
+            }
+            if (best_s < 0) {   // nothing fits the consumer: plain order, the consumer permutes
+                best_z = cat3(beta_o, best_m, best_n);
+                std::vector<int> zt = cat3(beta_o, best_n, best_m);
+                if (score(best_z, best_m, 0) < 0 && score(zt, best_m, 0) >= 0) best_z = zt;
+            }
+            m_o = best_m;
+            n_o = best_n;
+            if (attempt == 0 && best_s < 0 && Z.consumer >= 0) {
+                dropA = keepA && A.rank() < Z.rank();
+                dropB = keepB && B.rank() < Z.rank() && !dropA;
+                if (dropA || dropB) continue;
+            }
+            if (attempt == 1 && best_s < 0) {
+                dropA = dropB = false;
+                continue;
+            }
+            break;
         }
-        if (best_s < 0) {   // nothing fits the consumer: plain order, the consumer permutes
-            best_z = cat3(beta_o, best_m, best_n);
-            std::vector<int> zt = cat3(beta_o, best_n, best_m);
-            if (score(best_z, best_m, 0) < 0 && score(zt, best_m, 0) >= 0) best_z = zt;
-        }
-        m_o = best_m;
-        n_o = best_n;
         // operand orders
         if (keepA) {
             st.a_kc = oa;
