@@ -162,7 +162,7 @@ enum KernelId : int {
     K_DMA3_N64 = 14,  // FP16 3M from the DMA ring: 256 x 64 tile, two stages, two blocks per CU
     K_DMA3_2 = 15,    // FP16 3M, 128 x 128 tile, two stages, one wave per SIMD
     K_DMAP_2 = 16,    // 16-bit 4M, 128 x 128 tile, persistent over the launch's tiles, two stages
-    K_THINM = 17,     // 16-bit 4M thin steps (N = 4, 8 or 16) on 16 x 16 x 16 matrix-core tiles
+    K_THINM = 17,     // 16-bit 4M thin steps (N = 4 .. 32) on 16 x 16 x 16 matrix-core tiles
     K_COUNT = 18
 };
 const char *kernel_name(int k);

@@ -1155,7 +1155,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAG
     finish_max<true>(sc, s, mx);
 }
 
-// ===================================================================== thin on the matrix cores: N = 4, 8 or 16
+// ===================================================================== thin on the matrix cores: N = 4 .. 32
 //
 // The VALU thin kernel spends 4 FP32 FMAs per complex product (256 per row at
 // N = K = 8), which holds it near the VALU rate instead of the memory rate.
@@ -1938,9 +1938,11 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
     }
     if (kid == K_THINM) {
         // thin on the matrix cores: 4M, N = 4, 8 or 16, K a multiple of 8 up
-        // to 64 (16 when A is chunked along m), whole 64-row passes
+        // to 64 (16 when A is chunked along m); N = 32 with K up to 16; whole
+        // 64-row passes
         if (dt == Dtype::C64 || al != Algo::M4) return false;
-        if (!(g.N == 4 || g.N == 8 || g.N == 16) || g.K % 8 || g.K > (g.a_kc ? 64 : 16) || g.M % 64) return false;
+        if (!(g.N == 4 || g.N == 8 || g.N == 16 || g.N == 32) || g.K % 8 || g.M % 64) return false;
+        if (g.K > (g.a_kc && g.N <= 16 ? 64 : 16)) return false;
     }
     if (kid == K_DMAP_2) {
         // the persistent tile loop: as the DMA kernels (a two-stage ring spans
@@ -2120,7 +2122,10 @@ static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, co
         const bool short_k = g.K <= 16;   // the double-buffered A of a pass fits few registers
         if (!g.a_kc) {
             if (g.N <= 8) args(gemm_thinm_kernel<BF, 1, 2, false>);
-            else args(gemm_thinm_kernel<BF, 2, 2, false>);
+            else if (g.N <= 16) args(gemm_thinm_kernel<BF, 2, 2, false>);
+            else args(gemm_thinm_kernel<BF, 4, 2, false>);
+        } else if (g.N == 32) {
+            args(gemm_thinm_kernel<BF, 4, 2, true>);
         } else if (g.N <= 8) {
             if (short_k) args(gemm_thinm_kernel<BF, 1, 2, true>);
             else args(gemm_thinm_kernel<BF, 1, 8, true>);
