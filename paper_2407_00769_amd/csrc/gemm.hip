@@ -1375,7 +1375,7 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
 
 template <int BM, int BN, int WM, int WN, int STAGES>
 struct PTile {
-    using D = DTile<BM, BN, WM, WN, 2>;
+    using D = DTile<BM, BN, WM, WN, STAGES>;
     static constexpr int NT = D::NT, BK = D::BK;
     static constexpr int STAGE_BYTES = D::STAGE_BYTES;
     static constexpr int RING_BYTES = STAGES * STAGE_BYTES;
@@ -1414,7 +1414,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (PTile<BM, BN, WM, WN, STAGES>::
     gemm_dmap_h_kernel(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t *__restrict__ C,
                        GemmShape g, ScaleRefs sc, int S) {
     using Pt = PTile<BM, BN, WM, WN, STAGES>;
-    using Tl = DTile<BM, BN, WM, WN, 2>;
+    using Tl = DTile<BM, BN, WM, WN, STAGES>;
     using W = typename std::conditional<BF, Bf16Word, HalfWord>::type;
     constexpr int NT = Pt::NT, FM = Tl::FM, FC = Tl::FC, WTM = Tl::WTM, WTC = Tl::WTC, BK = Pt::BK;
     constexpr int LPT = Pt::LPT, NS = Pt::NS;
@@ -1466,8 +1466,8 @@ __global__ void __launch_bounds__(64 * WM * WN, (PTile<BM, BN, WM, WN, STAGES>::
             p.pb[i] = Bp + seg_offset(g.bn, it.n0 + 8 * (wave + i * (NT / 64)) + (lane >> 3)) + seg_offset(g.bk, 4 * dq);
         return p;
     };
-    auto issue = [&](const Ptrs &p, int64_t q, int kt) {
-        uint8_t *base = smem + (int)(q % STAGES) * Pt::STAGE_BYTES;
+    auto issue = [&](const Ptrs &p, int slot, int kt) {
+        uint8_t *base = smem + slot * Pt::STAGE_BYTES;
         const int64_t k0 = (int64_t)kt * BK;
         const int64_t ka = seg_offset(g.ak, k0), kb = seg_offset(g.bk, k0);
 #pragma unroll
@@ -1524,10 +1524,13 @@ __global__ void __launch_bounds__(64 * WM * WN, (PTile<BM, BN, WM, WN, STAGES>::
         nxt = item_of(1);
         pn = ptrs_of(nxt);
     }
-    const int64_t Q = n_items * nk;
+    // stage counters in 32 bits (the launcher checks the range); ring slots
+    // rotate without a division
+    const int Q = (int)(n_items * nk);
 #pragma unroll
     for (int st = 0; st < STAGES - 1; st++)
         if (st < Q) issue(pc, st, st);   // nk >= STAGES - 1: all in item 0
+    int slot_r = 0, slot_w = STAGES - 1;   // ring slots of stages q and q + STAGES - 1
 
     float mx = 0.f;           // running max of the stored values of slice cur.s
     int mx_slice = cur.s;
@@ -1550,25 +1553,26 @@ __global__ void __launch_bounds__(64 * WM * WN, (PTile<BM, BN, WM, WN, STAGES>::
                     acc[i][jj][0][r] = 0.f;
                     acc[i][jj][1][r] = 0.f;
                 }
-        const int64_t q0 = j * nk;
+        const int q0 = (int)j * nk;
         for (int kt = 0; kt < nk; kt++) {
-            const int64_t q = q0 + kt;
+            const int q = q0 + kt;
             {
-                const int64_t later = Q - 1 - q;
+                const int later = Q - 1 - q;
                 const int ahead = (int)(later < STAGES - 2 ? later : STAGES - 2);
                 // the previous tile's stores went out after this stage's loads
                 const bool epi = j > 0 && kt <= STAGES - 2;
                 pring_wait<STAGES, LPT, NS>(ahead, epi);
             }
             {
-                const int64_t qi = q + STAGES - 1;
-                if (qi < Q) {
+                if (q + STAGES - 1 < Q) {
                     const int kti = kt + STAGES - 1;
-                    if (kti < nk) issue(pc, qi, kti);
-                    else issue(pn, qi, kti - nk);
+                    if (kti < nk) issue(pc, slot_w, kti);
+                    else issue(pn, slot_w, kti - nk);
                 }
             }
-            const uint8_t *sb = smem + (int)(q % STAGES) * Pt::STAGE_BYTES;
+            const uint8_t *sb = smem + slot_r * Pt::STAGE_BYTES;
+            slot_r = slot_r == STAGES - 1 ? 0 : slot_r + 1;
+            slot_w = slot_w == STAGES - 1 ? 0 : slot_w + 1;
             u32x4 fa0[FM], fb0[FC], re0[FC], im0[FC], fa1[FM], fb1[FC], re1[FC], im1[FC];
             load(sb, 0, fa0, fb0);
             xform(fb0, re0, im0);
@@ -2102,6 +2106,9 @@ static void launch_dmap_cfg(const void *A, const void *B, void *C, const GemmSha
     const int64_t total = (int64_t)S * g.nb * (g.M / BM) * (g.N / BN);
     int64_t G = std::min<int64_t>(total, (int64_t)n_cu * Pt::BLOCKS_PER_CU);
     if (G >= 8) G &= ~(int64_t)7;
+    // a block's stage counter (items x k-tiles) runs in 32 bits
+    if ((total + G - 1) / G * (g.K / Pt::BK) >= ((int64_t)1 << 31))
+        TNC_THROW(TNC_EINVAL, "internal: too many tiles per block for the persistent tile loop");
     hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(Pt::NT), Pt::LDS_BYTES, st, (const uint32_t *)A,
                        (const uint32_t *)B, (uint32_t *)C, g, sc, S);
 }

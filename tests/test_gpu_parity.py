@@ -127,14 +127,16 @@ def test_contract_kernels(T, ctx, prec, kname, monkeypatch):
 # block walks two tiles and the ring runs on across their ends; k from one
 # 32-wide stage per tile to sixteen, and one batched case (the oracle's einsum
 # is slow on batch labels, so that one stays small)
-PERSISTENT_SHAPES = [(0, 14, 9, 5), (0, 13, 10, 6), (0, 15, 8, 7), (0, 12, 9, 9), (2, 11, 8, 5)]
+PERSISTENT_SHAPES = {
+    "dmap_2": [(0, 14, 9, 5), (0, 13, 10, 6), (0, 15, 8, 7), (0, 12, 9, 9), (2, 11, 8, 5)],
+}
 
 
 @pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m"])
 @pytest.mark.parametrize("kname", ["dmap_2"])
 def test_persistent_tile_loop(T, ctx, prec, kname, monkeypatch):
     monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
-    for i, (nb, m, n, k) in enumerate(PERSISTENT_SHAPES):
+    for i, (nb, m, n, k) in enumerate(PERSISTENT_SHAPES[kname]):
         _check_contract(T, ctx, prec, nb, m, n, k, seed=300 + i)
 
 
