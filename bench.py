@@ -49,7 +49,7 @@ def kernel_family(kid):
     return {0: "gemm_naive", 1: "gemm_skinny", 2: "gemm_mfma_s", 3: "gemm_mfma_m", 4: "gemm_mfma_l",
             5: "gemm_mfma_w", 6: "gemm_mfma_xl", 7: "gemm_mfma_l2", 8: "gemm_dma_4",
             9: "gemm_dma_8", 10: "gemm_dma_8w", 11: "gemm_dma_2", 12: "gemm_dma_n64", 13: "gemm_dma_n32", 14: "gemm_dma3_n64", 15: "gemm_dma3_2",
-            16: "gemm_dmap_2", 17: "gemm_thinm"}.get(int(kid), f"gemm_{kid}")
+            16: "gemm_dmap_2", 17: "gemm_thinm", 18: "gemm_dmap_n64"}.get(int(kid), f"gemm_{kid}")
 
 
 # ------------------------------------------------------------------ workloads

@@ -163,7 +163,8 @@ enum KernelId : int {
     K_DMA3_2 = 15,    // FP16 3M, 128 x 128 tile, two stages, one wave per SIMD
     K_DMAP_2 = 16,    // 16-bit 4M, 128 x 128 tile, persistent over the launch's tiles, two stages
     K_THINM = 17,     // 16-bit 4M thin steps (N = 4 .. 32) on 16 x 16 x 16 matrix-core tiles
-    K_COUNT = 18
+    K_DMAP_N64 = 18,  // the same on a 256 x 64 tile (2 x 2 waves, two blocks per CU): HBM-bound narrow steps
+    K_COUNT = 19
 };
 const char *kernel_name(int k);
 // Segments of the plain layouts ([m][k] or [k][m] etc., as the chunk flags

@@ -1360,8 +1360,11 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
 // boundaries: the first stage of tile j+1 is in flight while tile j's last
 // stage is multiplied and its result is stored (straight from the
 // accumulators), and the waits never cover the stores unless a later stage
-// needs them to.  Measured against the one-tile kernel on the same tile it
-// is level on K = 2^7 and 5-10% slower on K = 2^9; the autotuner picks.
+// needs them to.  On 128 x 128 tiles, measured against the one-tile kernel
+// on the same tile, it is level on K = 2^7 and 5-10% slower on K = 2^9.  On
+// 256 x 64 tiles with four waves it serves the HBM-bound N = 64 steps, whose
+// tiles hold two to four k-stages: 15-19% above the one-tile narrow kernels
+// there (about 5 TB/s).  The autotuner picks.
 //
 // Vector-memory ordering: the ring wait counts every vector memory
 // instruction issued after the awaited stage's loads -- the later stages'
@@ -1874,6 +1877,7 @@ const char *kernel_name(int k) {
         case K_DMA3_N64: return "dma3_n64";
         case K_DMA3_2: return "dma3_2";
         case K_DMAP_2: return "dmap_2";
+        case K_DMAP_N64: return "dmap_n64";
         case K_THINM: return "thinm";
         default: return "?";
     }
@@ -1908,6 +1912,7 @@ static TileCfg tile_of(int kid, Dtype dt, Algo al) {
             case K_DMA_N64: return {256, 64};
             case K_DMA_N32: return {256, 32};
             case K_DMAP_2: return {128, 128};
+            case K_DMAP_N64: return {256, 64};
             case K_THINM: return {64, 4};
         }
     } else {
@@ -1948,7 +1953,7 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
         if (!(g.N == 4 || g.N == 8 || g.N == 16 || g.N == 32) || g.K % 8 || g.M % 64) return false;
         if (g.K > (g.a_kc && g.N <= 16 ? 64 : 16)) return false;
     }
-    if (kid == K_DMAP_2) {
+    if (kid == K_DMAP_2 || kid == K_DMAP_N64) {
         // the persistent tile loop: as the DMA kernels (a two-stage ring spans
         // two tiles at most for any whole number of k-tiles)
         if (dt == Dtype::C64 || al != Algo::M4 || !g.a_kc || !g.b_kc) return false;
@@ -2117,6 +2122,7 @@ template <bool BF>
 static void launch_h(int kid, Algo al, const void *A, const void *B, void *C, const GemmShape &g, int S,
                      const ScaleRefs &sc, hipStream_t st) {
     if (kid == K_DMAP_2) return launch_dmap_cfg<BF, 128, 128, 2, 2, 2>(A, B, C, g, S, sc, st);
+    if (kid == K_DMAP_N64) return launch_dmap_cfg<BF, 256, 64, 2, 2, 2>(A, B, C, g, S, sc, st);
     if (kid == K_THINM) {
         // about 4096 blocks in all; each wave walks 64-row passes
         const int64_t units = g.M / 64, others = g.nb * (int64_t)S;
@@ -2201,7 +2207,7 @@ static void launch_c64(int kid, const void *A, const void *B, void *C, const Gem
 
 int64_t splitk_factor(int kid, Dtype dt, Algo al, const GemmShape &g, int S) {
     if (kid < K_MFMA_S || kid >= K_COUNT || !gemm_supported(kid, dt, al, g)) return 1;
-    if (kid == K_DMAP_2 || kid == K_THINM) return 1;
+    if (kid == K_DMAP_2 || kid == K_DMAP_N64 || kid == K_THINM) return 1;
     TileCfg t = tile_of(kid, dt, al);
     const int64_t bk = dt == Dtype::C64 ? 16 : 32;
     const int64_t blocks = (g.M / t.BM) * (g.N / t.BN) * g.nb * (int64_t)S;

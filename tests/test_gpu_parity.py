@@ -105,7 +105,7 @@ def _check_contract(T, ctx, prec, nb, m, n, k, seed, scale_log2=0):
 
 KERNELS = {"naive": 0, "skinny": 1, "mfma_s": 2, "mfma_m": 3, "mfma_l": 4, "mfma_w": 5, "mfma_xl": 6,
            "mfma_l2": 7, "dma_4": 8, "dma_8": 9, "dma_8w": 10, "dma_2": 11, "dma_n64": 12, "dma_n32": 13,
-           "dma3_n64": 14, "dma3_2": 15, "dmap_2": 16,
+           "dma3_n64": 14, "dma3_2": 15, "dmap_2": 16, "dmap_n64": 18,
            "thinm": 17}
 SHAPES = [  # nb, m, n, k  (log2)
     (0, 9, 6, 5), (1, 8, 5, 3), (0, 10, 4, 6), (2, 7, 7, 4), (0, 8, 0, 2), (0, 6, 3, 0), (0, 12, 5, 7),
@@ -129,11 +129,13 @@ def test_contract_kernels(T, ctx, prec, kname, monkeypatch):
 # is slow on batch labels, so that one stays small)
 PERSISTENT_SHAPES = {
     "dmap_2": [(0, 14, 9, 5), (0, 13, 10, 6), (0, 15, 8, 7), (0, 12, 9, 9), (2, 11, 8, 5)],
+    # 256 x 64 tiles, two blocks per CU: one, two and four tiles per block
+    "dmap_n64": [(0, 16, 7, 6), (0, 17, 7, 6), (0, 16, 8, 5), (0, 12, 8, 9), (1, 15, 7, 6)],
 }
 
 
 @pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m"])
-@pytest.mark.parametrize("kname", ["dmap_2"])
+@pytest.mark.parametrize("kname", ["dmap_2", "dmap_n64"])
 def test_persistent_tile_loop(T, ctx, prec, kname, monkeypatch):
     monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
     for i, (nb, m, n, k) in enumerate(PERSISTENT_SHAPES[kname]):
