@@ -569,10 +569,10 @@ def costmodel_study(torch, T, cn, workloads, restarts=32, seeds=(1, 2, 3, 4, 5))
     perm = rng.permutation(n)
     tr, te = perm[: int(0.8 * n)], perm[int(0.8 * n):]
     t0 = time.perf_counter()
-    Xw, yw = costmodel.weighted_rows(X[tr], y[tr])
+    Xw, yw = costmodel.training_rows(X[tr], y[tr])
     loss = T.tnc_mlp_train(ctx, Xw, yw, epochs=40, batch=256, lr=2e-3, seed=7)
     t_train = time.perf_counter() - t0
-    pred = T.tnc_mlp_predict(ctx, X[te])
+    pred = costmodel.predict(ctx, X[te])
     cfit = costmodel.flop_model_fit(fl[tr], y[tr])
     base = costmodel.flop_model_predict(fl[te], cfit)
     err_mlp = np.abs(pred - y[te])

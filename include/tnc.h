@@ -361,10 +361,8 @@ int tnc_mlp_adam(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32_
                  float *loss_out);
 /* Predict n rows (host in, host out).  After tnc_mlp_train or tnc_mlp_adam
  * the network is not asked to extrapolate in the size features (log2 M, N,
- * K, batch): a row above the range those training rows spanned is evaluated
- * at the top of the range and the excess (in log2 units) added to its
- * prediction, so time grows in proportion to the work beyond the data; a
- * row below the range is evaluated at its bottom.  Weights loaded with
+ * K, batch): each is clamped to the range the training rows spanned, so the
+ * output there is the value at the range's edge.  Weights loaded with
  * tnc_mlp_set_params carry no range and are evaluated as given. */
 int tnc_mlp_predict(tnc_ctx *ctx, int64_t n, const float *x, float *y_out);
 /* One forward + backward pass on n rows with the current weights: loss (MSE)
@@ -378,8 +376,19 @@ int64_t tnc_mlp_param_count(void);
 int tnc_mlp_get_params(tnc_ctx *ctx, float *params_out);
 int tnc_mlp_set_params(tnc_ctx *ctx, const float *params);
 /* Make the context's MLP the cost model used by tnc_search(cost_model = 1)
- * on this thread. */
+ * on this thread.  The search prices a step at
+ *     log2 t = tnc_costmodel_base(row) + MLP(row)   (microseconds),
+ * so the network is trained on y = log2(measured t) - tnc_costmodel_base(row):
+ * the learned part is the ratio of measured to roofline time, and a step
+ * unlike the training rows keeps the baseline's scaling with its work. */
 int tnc_costmodel_use(tnc_ctx *ctx);
+/* Roofline baseline of n feature rows (host in, host out; layout as above):
+ * log2 of 4 us plus the larger of the step's algorithmic flops (8 M N K per
+ * batch entry) at the matrix-core peak of its dtype (complex64: FP32 157.3
+ * TFLOP/s; FP16/BF16: 2516.6 TFLOP/s) and its bytes (A, B and C at the
+ * storage size, 8 or 4 bytes an entry, plus a read and a write of each
+ * operand of stride class 2) at 8 TB/s.  Host only; no context needed. */
+int tnc_costmodel_base(int64_t n, const float *x, float *log2_us_out);
 
 /* ------------------------------------------------------------------ low-precision exchange codec */
 

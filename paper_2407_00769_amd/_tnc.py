@@ -125,6 +125,7 @@ _SIGS = {
     "tnc_mlp_adam": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, ctypes.c_int32, ctypes.c_float,
                                     c_float_p]),
     "tnc_mlp_predict": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p]),
+    "tnc_costmodel_base": (ctypes.c_int, [ctypes.c_int64, c_float_p, c_float_p]),
     "tnc_mlp_grad": (ctypes.c_int, [vp, ctypes.c_int64, c_float_p, c_float_p, c_float_p, c_float_p]),
     "tnc_mlp_param_count": (ctypes.c_int64, []),
     "tnc_mlp_get_params": (ctypes.c_int, [vp, c_float_p]),
@@ -434,6 +435,16 @@ def tnc_mlp_predict(ctx, x):
     n = xa.shape[0]
     y = np.zeros(n, dtype=np.float32)
     _check(lib.tnc_mlp_predict(ctx, n, xp, y.ctypes.data_as(c_float_p)))
+    return y
+
+
+def tnc_costmodel_base(x):
+    """Roofline baseline (log2 us) of feature rows: the part of the search's
+    step cost that the MLP does not learn."""
+    xa, xp = _f32(x)
+    n = xa.shape[0]
+    y = np.zeros(n, dtype=np.float32)
+    _check(lib.tnc_costmodel_base(n, xp, y.ctypes.data_as(c_float_p)))
     return y
 
 

@@ -12,6 +12,12 @@ where batch counts the inner batch times the slices the launch carries,
 stride class is 0 (operand read in place as [free][k]), 1 (in place as
 [k][free]) or 2 (permuted first), dtype is 0 complex64, 1 FP16, 2 BF16 and
 algorithm is 0 for 4M, 1 for 3M.
+
+The model the search uses is the library's roofline baseline of a row
+(tnc_costmodel_base: launch latency plus the larger of flops at peak and
+bytes at 8 TB/s) plus the MLP's output, so the MLP is trained on the log2
+ratio of measured to baseline time (training_rows) and predictions add the
+baseline back (predict).
 """
 from __future__ import annotations
 
@@ -100,6 +106,18 @@ def weighted_rows(X, y, base_us=16.0, cap=16):
     return X[idx], y[idx]
 
 
+def training_rows(X, y):
+    """Weighted rows with the MLP's target: log2 of measured over baseline time."""
+    Xw, yw = weighted_rows(X, y)
+    return Xw, (yw - T.tnc_costmodel_base(Xw)).astype(np.float32)
+
+
+def predict(ctx, X):
+    """The cost model's log2 step time (us): baseline plus the trained MLP."""
+    X = np.asarray(X, np.float32)
+    return T.tnc_mlp_predict(ctx, X) + T.tnc_costmodel_base(X)
+
+
 def flop_model_fit(flops, y):
     """The FLOP cost model with its one scale fitted: log2 t = log2 flops + c."""
     return float(np.median(np.asarray(y, np.float64) - np.log2(np.maximum(flops, 1.0))))
@@ -131,7 +149,7 @@ def path_prediction(ctx, plan, bits, n_slices, prec):
         X.append([m, n, k, b + math.log2(per_launch_slices), sa, sb, DTYPE_CODE[prec], ALGO_CODE[prec]])
         mult.append(float(launches[i]))
         measured += float(g[i] + p[i])
-    pred = T.tnc_mlp_predict(ctx, np.array(X, np.float32))
+    pred = predict(ctx, np.array(X, np.float32))
     return measured, float(np.sum(np.exp2(pred.astype(np.float64)) * np.array(mult)) * 1e-3)
 
 
@@ -151,5 +169,5 @@ def search_estimate(ctx, net, ssa, sliced, open_q, slices_per_launch, prec="f16_
         sa, sb = a["perm_ab"][i]
         X.append([m, n, k, b + (math.log2(S) if dep else 0.0), sa, sb, DTYPE_CODE[prec], ALGO_CODE[prec]])
         mult.append(total / S if dep else 1.0)
-    pred = T.tnc_mlp_predict(ctx, np.array(X, np.float32))
+    pred = predict(ctx, np.array(X, np.float32))
     return float(np.sum(np.exp2(pred.astype(np.float64)) * np.array(mult)) * 1e-3)

@@ -1,8 +1,12 @@
 // Learned step-cost model: a 3-layer MLP (in -> 128 -> 128 -> 1, ReLU, FP32)
-// that predicts log2 of a contraction step's device time in microseconds
-// from its shape features.  It is trained on the device by the kernels below
-// (forward, backward, Adam) on timings the engine measures, and it ranks the
-// candidate paths of tnc_search (cost_model = 1).
+// trained on the device by the kernels below (forward, backward, Adam) on
+// timings the engine measures.  As the search's cost model it predicts a
+// step's log2 device time in microseconds as a roofline baseline computed
+// from the same features (step_base_log2_us) plus the network's output, the
+// learned log2 ratio of measured to baseline time; it ranks the candidate
+// paths of tnc_search (cost_model = 1).  A step unlike any training row then
+// keeps the baseline's scaling with its work instead of an extrapolation of
+// the network.
 //
 // Parameter layout (one float array): W1[128][F], b1[128], W2[128][128], b2[128],
 // W3[1][128], b3[1].  Inputs are multiplied by a fixed per-feature scale
@@ -252,6 +256,23 @@ static void init_params(Mlp *m, uint64_t seed, hipStream_t st) {
 }
 
 // Host-side path cost for the search: sum of predicted step times.
+// Roofline baseline of a step (log2 microseconds) from its feature row: a
+// launch latency of 4 us plus the larger of its algorithmic flops (8 M N K
+// per batch entry) at the matrix-core peak of its dtype (FP32 157.3 TFLOP/s
+// for complex64, FP16/BF16 2516.6) and its bytes (A, B and C at the storage
+// size, 8 or 4 bytes an entry, plus a read and a write of each permuted
+// operand) at 8 TB/s.
+double step_base_log2_us(const float *f) {
+    const double m = f[0], n = f[1], k = f[2], b = f[3];
+    const bool c64 = f[6] < 0.5f;
+    const double s = c64 ? 8.0 : 4.0, peak = c64 ? 157.3e12 : 2516.6e12;
+    const double flops = 8.0 * std::exp2(m + n + k + b);
+    double bytes = s * (std::exp2(b + m + k) + std::exp2(b + n + k) + std::exp2(b + m + n));
+    if (f[4] > 1.5f) bytes += 2.0 * s * std::exp2(b + m + k);
+    if (f[5] > 1.5f) bytes += 2.0 * s * std::exp2(b + n + k);
+    return std::log2(4.0 + 1e6 * std::max(flops / peak, bytes / 8e12));
+}
+
 double mlp_path_cost(const Network &net, const std::vector<int> &ssa, const std::vector<int> &sliced,
                      const std::vector<int> &open_q) {
     tnc_ctx *ctx = g_cost_ctx;
@@ -281,7 +302,7 @@ double mlp_path_cost(const Network &net, const std::vector<int> &ssa, const std:
     std::vector<float> y(mult.size());
     if (tnc_mlp_predict(ctx, (int64_t)mult.size(), x.data(), y.data()) != TNC_OK) return -1.0;
     double c = 0;
-    for (size_t i = 0; i < y.size(); i++) c += mult[i] * std::exp2((double)y[i]);
+    for (size_t i = 0; i < y.size(); i++) c += mult[i] * std::exp2((double)y[i] + step_base_log2_us(&x[i * F]));
     return c;
 }
 
@@ -303,6 +324,14 @@ template <typename Fn> static int guard(Fn fn) {
 }
 
 extern "C" int64_t tnc_mlp_param_count(void) { return NPARAM; }
+
+extern "C" int tnc_costmodel_base(int64_t n, const float *x, float *log2_us_out) {
+    return guard([&] {
+        if (n < 0) TNC_THROW(TNC_EINVAL, "n < 0");
+        if (n > 0 && (!x || !log2_us_out)) TNC_THROW(TNC_EINVAL, "NULL argument");
+        for (int64_t r = 0; r < n; r++) log2_us_out[r] = (float)step_base_log2_us(x + r * F);
+    });
+}
 
 extern "C" int tnc_mlp_train(tnc_ctx *ctx, int64_t n, const float *x, const float *y, int32_t epochs, int32_t batch,
                              float lr, uint64_t seed, float *loss_out) {
@@ -391,24 +420,16 @@ extern "C" int tnc_mlp_predict(tnc_ctx *ctx, int64_t n, const float *x, float *y
         Mlp *m = mlp_of(ctx);
         ensure_rows(m, n);
         // Outside the trained size range the network is not asked to
-        // extrapolate: a size feature above the range is taken at its top
-        // and the excess added to the log2 time (time grows in proportion to
-        // the work there); one below the range is taken at its bottom.
+        // extrapolate: a size feature is clamped to the range, so the learned
+        // ratio to the roofline baseline is held at its edge value there.
         std::vector<float> xc;
-        std::vector<float> excess;
         const float *xs = x;
         if (m->support) {
             xc.assign(x, x + n * F);
-            excess.assign(n, 0.f);
             for (int64_t r = 0; r < n; r++)
                 for (int f = 0; f < 4; f++) {
                     float &v = xc[r * F + f];
-                    if (v > m->hi[f]) {
-                        excess[r] += v - m->hi[f];
-                        v = m->hi[f];
-                    } else if (v < m->lo[f]) {
-                        v = m->lo[f];
-                    }
+                    v = std::min(std::max(v, m->lo[f]), m->hi[f]);
                 }
             xs = xc.data();
         }
@@ -416,8 +437,6 @@ extern "C" int tnc_mlp_predict(tnc_ctx *ctx, int64_t n, const float *x, float *y
         forward(m, m->x, nullptr, n, st);
         HIP_CHECK(hipMemcpyAsync(y_out, m->out, n * sizeof(float), hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
-        if (m->support)
-            for (int64_t r = 0; r < n; r++) y_out[r] += excess[r];
     });
 }
 

@@ -15,7 +15,9 @@
 //   4. across restarts, the (path, sliced labels) with the least cost: total
 //      FLOPs, or the learned step-time model's prediction when one is active;
 //      the same cost also picks between a restart's greedy variants and
-//      decides whether a reconfigured tree is kept.
+//      decides whether a reconfigured tree is kept.  Under the learned model
+//      the FLOP-cost search runs first and its choice stays unless the
+//      model's own search finds a path it predicts to be faster.
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -433,95 +435,120 @@ extern "C" int tnc_search(const tnc_network *net_h, int32_t n_open, const int32_
             sliceable[net.output_labels[q]] = 0;
             if (!is_open[q]) gone[net.output_labels[q]] = 1;   // closed: fixed per call
         }
-        std::mt19937_64 rng(seed);
-        std::uniform_real_distribution<double> ua(0.6, 1.6), ut(0.0, 1.0);
-        double best_cost = 1e300;
-        std::vector<int> best_ssa, best_sl;
-        double best_flops = 0;
         const char *rc = getenv("TNC_SEARCH_RECONF");
         const int reconf_rounds = rc ? atoi(rc) : 8;
-        // Cost of a candidate (log2): total flops under the FLOP model, or the
-        // learned model's predicted device time of the path the plan would
-        // run; it picks between the greedy variants of a restart, decides
-        // whether a reconfigured tree replaces the current one, and ranks the
-        // restarts.
-        auto cost_of = [&](const Tree &tr, const Sliced &sv) -> double {
-            if (cost_model == 1) {
-                double c = mlp_path_cost(net, tr.ssa, sv.labels, open_q);
-                if (c > 0) return std::log2(c);
-            }
-            return sv.log2_total;
+        struct Best {
+            double cost = 1e300, flops = 0;
+            std::vector<int> ssa, sl;
         };
-        for (int r = 0; r < restarts; r++) {
-            double alpha = r == 0 ? 1.0 : ua(rng);
-            double temp = r == 0 ? 0.0 : ut(rng) * ut(rng);
-            std::vector<char> sl(L, 0);
-            Tree t;
-            Sliced s;
-            double s_cost = 0;
-            for (int it = 0; it < 3; it++) {
-                std::vector<char> g2 = gone;
-                for (int l = 0; l < L; l++)
-                    if (sl[l]) g2[l] = 1;
-                Tree cand = greedy(reduced_inputs(net, g2), L, alpha, temp, rng);
-                // the tree's labels must include the sliced ones for slice_tree's bookkeeping
-                Tree full = cand;
-                {
-                    auto in = reduced_inputs(net, gone);
-                    full.labels.assign(in.begin(), in.end());
-                    full.labels.resize(2 * net.n_tensors - 1);
-                    full.uni.clear();
-                    std::vector<int> u;
-                    for (size_t st = 0; st < cand.ssa.size() / 2; st++) {
-                        full.labels[net.n_tensors + st] = symdiff(full.labels[cand.ssa[2 * st]], full.labels[cand.ssa[2 * st + 1]], &u);
-                        full.uni.push_back(u);
+        // One pass of restarts from the seed.  Cost of a candidate (log2): total
+        // flops under the FLOP model, or the learned model's predicted device
+        // time of the path the plan would run; it picks between the greedy
+        // variants of a restart, decides whether a reconfigured tree replaces
+        // the current one, and ranks the restarts.
+        auto search_pass = [&](bool use_mlp) {
+            std::mt19937_64 rng(seed);
+            std::uniform_real_distribution<double> ua(0.6, 1.6), ut(0.0, 1.0);
+            double best_cost = 1e300;
+            std::vector<int> best_ssa, best_sl;
+            double best_flops = 0;
+            auto cost_of = [&](const Tree &tr, const Sliced &sv) -> double {
+                if (use_mlp) {
+                    double c = mlp_path_cost(net, tr.ssa, sv.labels, open_q);
+                    if (c > 0) return std::log2(c);
+                }
+                return sv.log2_total;
+            };
+            for (int r = 0; r < restarts; r++) {
+                double alpha = r == 0 ? 1.0 : ua(rng);
+                double temp = r == 0 ? 0.0 : ut(rng) * ut(rng);
+                std::vector<char> sl(L, 0);
+                Tree t;
+                Sliced s;
+                double s_cost = 0;
+                for (int it = 0; it < 3; it++) {
+                    std::vector<char> g2 = gone;
+                    for (int l = 0; l < L; l++)
+                        if (sl[l]) g2[l] = 1;
+                    Tree cand = greedy(reduced_inputs(net, g2), L, alpha, temp, rng);
+                    // the tree's labels must include the sliced ones for slice_tree's bookkeeping
+                    Tree full = cand;
+                    {
+                        auto in = reduced_inputs(net, gone);
+                        full.labels.assign(in.begin(), in.end());
+                        full.labels.resize(2 * net.n_tensors - 1);
+                        full.uni.clear();
+                        std::vector<int> u;
+                        for (size_t st = 0; st < cand.ssa.size() / 2; st++) {
+                            full.labels[net.n_tensors + st] = symdiff(full.labels[cand.ssa[2 * st]], full.labels[cand.ssa[2 * st + 1]], &u);
+                            full.uni.push_back(u);
+                        }
+                    }
+                    Sliced sc = slice_tree(full, L, sliceable, log2_cap, sl);
+                    const double c = cost_of(full, sc);
+                    if (it == 0 || c < s_cost) {
+                        t = full;
+                        s = sc;
+                        s_cost = c;
+                    }
+                    std::fill(sl.begin(), sl.end(), 0);
+                    for (int l : s.labels) sl[l] = 1;
+                }
+                if (s.max_rank > log2_cap) continue;
+                // local improvement: reconfigure sub-trees under the cap with the sliced
+                // labels removed, then re-slice (the cap may now need fewer labels)
+                if (reconf_rounds > 0) {
+                    auto inputs = reduced_inputs(net, gone);
+                    for (int rr = 0; rr < 2; rr++) {
+                        std::vector<char> slv(L, 0);
+                        for (int l : s.labels) slv[l] = 1;
+                        BTree bt = to_btree(t, net.n_tensors, slv);
+                        for (int q = 0; q < reconf_rounds; q++)
+                            if (reconfigure_once(bt, log2_cap, rng) == 0) break;
+                        Tree t2 = tree_from_ssa(inputs, btree_ssa(bt));
+                        // drop sliced labels the new tree no longer needs, most expensive first
+                        std::vector<char> sl2(L, 0);
+                        Sliced s2 = slice_tree(t2, L, sliceable, log2_cap, sl2);
+                        Sliced s3 = slice_tree(t2, L, sliceable, log2_cap, slv);
+                        Sliced &pick = (s2.log2_total <= s3.log2_total) ? s2 : s3;
+                        const double c2 = pick.max_rank <= log2_cap ? cost_of(t2, pick) : 1e300;
+                        if (c2 < s_cost) {
+                            t = t2;
+                            s = pick;
+                            s_cost = c2;
+                        } else {
+                            break;
+                        }
                     }
                 }
-                Sliced sc = slice_tree(full, L, sliceable, log2_cap, sl);
-                const double c = cost_of(full, sc);
-                if (it == 0 || c < s_cost) {
-                    t = full;
-                    s = sc;
-                    s_cost = c;
-                }
-                std::fill(sl.begin(), sl.end(), 0);
-                for (int l : s.labels) sl[l] = 1;
-            }
-            if (s.max_rank > log2_cap) continue;
-            // local improvement: reconfigure sub-trees under the cap with the sliced
-            // labels removed, then re-slice (the cap may now need fewer labels)
-            if (reconf_rounds > 0) {
-                auto inputs = reduced_inputs(net, gone);
-                for (int rr = 0; rr < 2; rr++) {
-                    std::vector<char> slv(L, 0);
-                    for (int l : s.labels) slv[l] = 1;
-                    BTree bt = to_btree(t, net.n_tensors, slv);
-                    for (int q = 0; q < reconf_rounds; q++)
-                        if (reconfigure_once(bt, log2_cap, rng) == 0) break;
-                    Tree t2 = tree_from_ssa(inputs, btree_ssa(bt));
-                    // drop sliced labels the new tree no longer needs, most expensive first
-                    std::vector<char> sl2(L, 0);
-                    Sliced s2 = slice_tree(t2, L, sliceable, log2_cap, sl2);
-                    Sliced s3 = slice_tree(t2, L, sliceable, log2_cap, slv);
-                    Sliced &pick = (s2.log2_total <= s3.log2_total) ? s2 : s3;
-                    const double c2 = pick.max_rank <= log2_cap ? cost_of(t2, pick) : 1e300;
-                    if (c2 < s_cost) {
-                        t = t2;
-                        s = pick;
-                        s_cost = c2;
-                    } else {
-                        break;
-                    }
+                const double cost = s_cost;
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_ssa = t.ssa;
+                    best_sl = s.labels;
+                    best_flops = s.log2_total;
                 }
             }
-            const double cost = s_cost;
-            if (cost < best_cost) {
-                best_cost = cost;
-                best_ssa = t.ssa;
-                best_sl = s.labels;
-                best_flops = s.log2_total;
+            Best b;
+            b.cost = best_cost;
+            b.flops = best_flops;
+            b.ssa = best_ssa;
+            b.sl = best_sl;
+            return b;
+        };
+        // Under the learned model the FLOP pass's choice is ranked beside the
+        // model's own: the model leaves the FLOP path only for one it predicts
+        // to be faster (the two passes search different candidate sets).
+        Best pick = search_pass(false);
+        if (cost_model == 1 && !pick.ssa.empty()) {
+            const double cf = mlp_path_cost(net, pick.ssa, pick.sl, open_q);
+            if (cf > 0) {
+                Best m = search_pass(true);
+                if (!m.ssa.empty() && m.cost < std::log2(cf)) pick = m;
             }
         }
+        const std::vector<int> &best_ssa = pick.ssa, &best_sl = pick.sl;
+        const double best_flops = pick.flops;
         if (best_ssa.empty()) TNC_THROW(TNC_EINVAL, "no path meets the memory cap");
         if ((int)best_sl.size() > max_sliced) TNC_THROW(TNC_EINVAL, "more sliced labels than max_sliced");
         std::copy(best_ssa.begin(), best_ssa.end(), ssa_out);
