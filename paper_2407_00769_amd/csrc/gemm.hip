@@ -1166,7 +1166,8 @@ __global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAG
 // (bi, br) for d = 1 (4M), so lanes 2n and 2n+1 hold Re and Im of complex
 // column n and swap them with one DPP quad permute (columns n >= N are zero).
 // A wave takes 64 rows per pass.  A chunked along k: one 8-byte load per
-// lane reads 16 whole rows.  A chunked along m: the pass's K x 64 entries
+// lane reads 16 whole rows (K = 2 or 4 fill one k chunk in part: the lanes
+// past K load nothing and hold zeros in A and B').  A chunked along m: the pass's K x 64 entries
 // come in 16-byte chunks along m and go through an LDS region of the wave's
 // own, read back k-major.  The next pass's A is loaded before this pass's
 // result is staged (LDS, [row][n] words) and stored in 16-byte chunks; for
@@ -1212,7 +1213,10 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
     const uint32_t *Bp = B + s * g.sB + b_block(g, b) * g.bB;
     uint32_t *Cp = C + s * g.sC + b * g.bC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int kc = (int)(g.K / 8), nn = (int)g.N;
+    // k chunks of 8 complex; K = 2 or 4 is one chunk whose lanes past K hold
+    // zeros in both operands (lane l covers complex k 8t + 2(l/16), + 1)
+    const int kk = (int)g.K, kc = (kk + 7) / 8, nn = (int)g.N;
+    const bool klane = 2 * (lane >> 4) < kk;   // this lane's k pair exists in chunk 0
     const bool odd = (lane & 1) != 0;
     // padded B' operands of every k chunk and column block
     u32x2 bop[KCM][NB];
@@ -1222,7 +1226,7 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
         for (int q = 0; q < NB; q++) {
             u32x2 v = {0u, 0u};
             const int n = q * 8 + (lane & 15) / 2;
-            if (t < kc && n < nn) {
+            if (t < kc && n < nn && (t > 0 || klane)) {
                 const int64_t k = 8 * t + 2 * (lane >> 4);
 #pragma unroll
                 for (int e = 0; e < 2; e++) {
@@ -1250,14 +1254,16 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
                 const uint32_t *ap = Ap + seg_offset(g.am, m0 + 16 * gq + (lane & 15));
 #pragma unroll
                 for (int t = 0; t < KCM; t++)
-                    if (t < kc) r.a[gq][t] = *(const u32x2 *)(ap + seg_offset(g.ak, 8 * t + 2 * (lane >> 4)));
+                    if (t < kc)
+                        r.a[gq][t] = (t > 0 || klane) ? *(const u32x2 *)(ap + seg_offset(g.ak, 8 * t + 2 * (lane >> 4)))
+                                                      : u32x2{0u, 0u};
             }
         } else {
             // chunk c: k = c / 16, rows 4 (c % 16)..+3
 #pragma unroll
             for (int i = 0; i < NCH; i++) {
                 const int c = i * 64 + lane, k = c >> 4, m4 = (c & 15) * 4;
-                if (k < 8 * kc) r.c[i] = *(const u32x4 *)(Ap + seg_offset(g.am, m0 + m4) + seg_offset(g.ak, k));
+                if (k < kk) r.c[i] = *(const u32x4 *)(Ap + seg_offset(g.am, m0 + m4) + seg_offset(g.ak, k));
             }
         }
     };
@@ -1267,7 +1273,7 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
 #pragma unroll
             for (int i = 0; i < NCH; i++) {
                 const int c = i * 64 + lane, k = c >> 4, m4 = (c & 15) * 4;
-                if (k < 8 * kc) *(u32x4 *)(as + k * AS + m4) = r.c[i];
+                if (k < kk) *(u32x4 *)(as + k * AS + m4) = r.c[i];
             }
             wave_lds_wait();
 #pragma unroll
@@ -1276,7 +1282,7 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
                 for (int t = 0; t < KCM; t++)
                     if (t < kc) {
                         const int k = 8 * t + 2 * (lane >> 4), m = 16 * gq + (lane & 15);
-                        r.a[gq][t] = u32x2{as[k * AS + m], as[(k + 1) * AS + m]};
+                        r.a[gq][t] = (t > 0 || klane) ? u32x2{as[k * AS + m], as[(k + 1) * AS + m]} : u32x2{0u, 0u};
                     }
             wave_lds_wait();   // read out before the next pass writes
         }
@@ -1961,12 +1967,18 @@ bool gemm_supported(int kid, Dtype dt, Algo al, const GemmShape &g) {
         if (g.K % 32) return false;
     }
     if (kid == K_THINM) {
-        // thin on the matrix cores: 4M, N = 4, 8 or 16, K a multiple of 8 up
-        // to 64 (16 when A is chunked along m); N = 32 with K up to 16; whole
-        // 64-row passes
+        // thin on the matrix cores: 4M, N = 4, 8 or 16, K = 2, 4 or a multiple
+        // of 8 up to 64 (16 when A is chunked along m); N = 32 with K up to
+        // 16; whole 64-row passes
         if (dt == Dtype::C64 || al != Algo::M4) return false;
-        if (!(g.N == 4 || g.N == 8 || g.N == 16 || g.N == 32) || g.K % 8 || g.M % 64) return false;
+        if (!(g.N == 4 || g.N == 8 || g.N == 16 || g.N == 32) || g.M % 64) return false;
+        if (g.K % 8 && g.K != 2 && g.K != 4) return false;
         if (g.K > (g.a_kc && g.N <= 16 ? 64 : 16)) return false;
+        // its own access rules: A in 8-byte pairs of k (chunked along k) or
+        // 16-byte chunks of m, B entry by entry, C in 16-byte chunks
+        auto run = [&](const Seg &sg, int64_t ext, int lo) { return sg.ls == 0 && seg_low_run(sg, ext) >= lo; };
+        if (!(g.a_kc ? run(g.ak, g.K, 1) : run(g.am, g.M, 2))) return false;
+        return g.c_nc ? run(g.cn, g.N, 2) : run(g.cm, g.M, 2);
     }
     if (kid == K_DMAP_2 || kid == K_DMAP_N64) {
         // the persistent tile loop: as the DMA kernels (a two-stage ring spans

@@ -145,7 +145,8 @@ def test_persistent_tile_loop(T, ctx, prec, kname, monkeypatch):
 # thin steps on the matrix cores: N = 4, 8 or 16 complex columns, K = 8..64,
 # one to four 64-row passes per wave and batches of up to four
 THIN_SHAPES = [(0, 12, 3, 3), (1, 11, 3, 4), (0, 13, 4, 4), (2, 10, 4, 6), (0, 6, 3, 3), (0, 10, 4, 5),
-               (0, 12, 2, 3), (1, 10, 2, 4), (0, 12, 5, 3), (1, 10, 5, 4), (0, 6, 5, 3)]
+               (0, 12, 2, 3), (1, 10, 2, 4), (0, 12, 5, 3), (1, 10, 5, 4), (0, 6, 5, 3),
+               (0, 12, 3, 1), (0, 12, 2, 2), (1, 10, 4, 1), (0, 11, 5, 2)]   # K = 2, 4: one partial chunk
 
 
 @pytest.mark.parametrize("prec", ["f16_4m", "bf16_4m"])
@@ -155,9 +156,9 @@ def test_thin_matrix_core_kernel(T, ctx, prec, monkeypatch):
         _check_contract(T, ctx, prec, nb, m, n, k, seed=400 + i)
     # read and written in place: A as [m][k] or [k][m] (the latter through
     # LDS), B as [n][k] or [k][n], C as [m][n] or [n][m]; N = 4, 8, 16, 32;
-    # K = 8, 16
+    # K = 2, 4, 8, 16
     rng = np.random.default_rng(14)
-    for n, k, a_kc, b_kc, c_nc in itertools.product((2, 3, 4, 5), (3, 4), (1, 0), (1, 0), (1, 0)):
+    for n, k, a_kc, b_kc, c_nc in itertools.product((2, 3, 4, 5), (1, 2, 3, 4), (1, 0), (1, 0), (1, 0)):
         al, bl, cl, a, b = _oriented_case(rng, 9, n, k, a_kc, b_kc, c_nc)
         A, av = to_storage(a, prec)
         B, bv = to_storage(b, prec)
