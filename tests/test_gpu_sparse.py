@@ -83,6 +83,30 @@ def test_sparse_state_matches_state_vector(T, ctx, case, prec):
     T.tnc_plan_destroy(plan)
 
 
+@pytest.mark.parametrize("prec", ["c64", "f16_4m"])
+def test_sparse_state_on_a_path_searched_with_open_outputs(T, ctx, case, prec):
+    """The path the sparse study uses: searched with every output leg open,
+    so the output legs enter late (here with two sliced labels); the sparse
+    plan keeps those legs as blocks, and its amplitudes match the state
+    vector."""
+    r_len = len(case["ssa"]) // 2 + 1
+    ssa, sl, _ = T.tnc_search(case["net"], r_len, list(range(16)), 16, restarts=4, seed=1)
+    assert len(sl) >= 1
+    plan = T.tnc_plan_create_sparse(ctx, case["net"], ssa, sl, case["bits"], prec)
+    n = 1 << len(sl)
+    out, _ = T.tnc_execute(plan, case["bits"], 0, n)
+    f = metrics.fidelity(case["ref"], out)
+    rl = metrics.rel_l2(out, case["ref"])
+    rm = metrics.rel_max(out, case["ref"])
+    print(prec, "fidelity", f, "rel_l2", rl, "rel_max", rm)
+    if prec == "c64":
+        assert f >= 1 - 1e-8 and rl <= 1e-5 and rm <= 1e-5, (f, rl, rm)
+    else:
+        assert f >= 0.999 and rl <= 0.02 and rm <= 0.03, (f, rl, rm)
+    np.testing.assert_array_equal(out[-5:], out[:5])
+    T.tnc_plan_destroy(plan)
+
+
 def test_sparse_state_equals_dense_plan_on_a_subspace(T, ctx, case):
     """Bitstrings that do share a prefix: the sparse plan (which is not told so)
     and the dense correlated-subspace plan give the same amplitudes."""
