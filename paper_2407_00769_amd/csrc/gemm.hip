@@ -1170,9 +1170,9 @@ __global__ void __launch_bounds__(64 * WM * WN, (dma_min_blocks<M3, BM, BN, STAG
 // past K load nothing and hold zeros in A and B').  A chunked along m: the pass's K x 64 entries
 // come in 16-byte chunks along m and go through an LDS region of the wave's
 // own, read back k-major.  The next pass's A is loaded before this pass's
-// result is staged (LDS, [row][n] words) and stored in 16-byte chunks; for
-// K up to 16 into a second register buffer, above that into the one the
-// matrix cores have just read.
+// result is staged (LDS, [row][n] words) and stored in 16-byte chunks, into
+// the register buffer the matrix cores have just read (a second buffer only
+// for N <= 8 with A chunked along k and K <= 16).
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short short4_t __attribute__((ext_vector_type(4)));
@@ -1347,11 +1347,13 @@ __global__ void __launch_bounds__(256) gemm_thinm_kernel(const uint32_t *__restr
         wave_lds_wait();   // read out before the next pass writes
     };
     int64_t u = (int64_t)blockIdx.x * 4 + wave;
-    if constexpr (KCM == 8) {
+    if constexpr (!(NB == 1 && AKC && KCM == 2)) {
         // one buffer: the next pass loads into it once this pass's matrix-core
-        // work has taken its operands.  Half the registers of two buffers, so
-        // twice the waves per SIMD: with N = 16 the K = 32..64 steps move
-        // 4.6-5.0 TB/s instead of 3.4-3.9
+        // work has taken its operands, and the loads are in flight during the
+        // epilogue either way.  Fewer registers, more waves per SIMD: with
+        // N = 16 the K = 32..64 steps move 4.6-5.0 TB/s instead of 3.4-3.9, and
+        // with A chunked along m the short-k steps gain 12-36%.  (The
+        // smallest variant already runs four waves per SIMD and keeps two.)
         Raw r0;
         if (u < units) load_pass(u, r0);
         while (u < units) {
