@@ -174,6 +174,20 @@ def test_thin_matrix_core_kernel(T, ctx, prec, monkeypatch):
         assert np.all(err <= bound), (prec, n, k, a_kc, b_kc, c_nc, float(np.max(err / bound)))
 
 
+@pytest.mark.parametrize("kname", ["dma_2", "dma_8w", "dmap_2"])
+def test_large_result(T, ctx, kname, monkeypatch):
+    """A 2^14 x 2^12 result (2^26 FP16 complex entries, 256 MB, more than the
+    caches hold) through the one-tile and persistent kernels against the
+    oracle."""
+    monkeypatch.setenv("TNC_FORCE_KERNEL", str(KERNELS[kname]))
+    ws = torch.empty(2 << 30, dtype=torch.uint8, device="cuda:0")   # room for permuted copies
+    big = T.tnc_create(0, ws, stream=torch.cuda.Stream())
+    _check_contract(T, big, "f16_4m", 0, 14, 12, 5, seed=520)
+    T.tnc_destroy(big)
+    torch.cuda.synchronize()
+    del ws
+
+
 def _oriented_case(rng, m, n, k, a_kc, b_kc, c_nc):
     ml = list(range(0, m))
     nl = list(range(m, m + n))
