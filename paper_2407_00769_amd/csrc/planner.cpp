@@ -414,6 +414,20 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         // block; below it the free and the reduced labels may each lie in at
         // most two runs, and the lowest run must hold a whole chunk.  Returns
         // the length of that lowest run (bits) and its group, or 0.
+        // The thin matrix-core kernel reads A in 8-byte pairs of k, so where a
+        // step is one it takes (N = 4..32, K = 2, 4 or 8..64, 64 rows or more)
+        // a lowest reduced run of one bit will do.  That is a last resort:
+        // where the 16-byte rule finds an in-place order it stands, since
+        // accepting the looser orders everywhere leads later steps into worse
+        // layouts (53-qubit path: 22 -> 36 GB of permutes per slice).
+        int lq_k = lq;   // the run a lowest reduced group needs
+        auto thin_ok = [&](const StepRec &t) {
+            const int64_t N = (int64_t)1 << t.n.size(), K = (int64_t)1 << t.k.size();
+            if (an.dt == Dtype::C64 || an.al != Algo::M4 || t.m.size() < 6) return false;
+            if (!(N == 4 || N == 8 || N == 16 || N == 32)) return false;
+            if (!(K == 2 || K == 4 || (K % 8 == 0 && K <= 64))) return false;
+            return !(N == 32 && K > 16);
+        };
         auto inplace = [&](const std::vector<int> &order, const std::vector<int> &g, int &low_group) -> int {
             const int r = (int)order.size();
             int pos = 0;
@@ -437,7 +451,7 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
                 return 0;
             }
             low_group = last;
-            return low_len >= lq ? low_len : 0;
+            return low_len >= (last == 2 ? lq_k : lq) ? low_len : 0;
         };
         auto orient = [&](const TensorRec &T) -> int {
             if (T.leaf) return -1;
@@ -446,6 +460,11 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             return lg == 2 ? 1 : 0;
         };
         int oa = orient(A), ob = orient(B);
+        if (oa < 0 && !A.leaf && thin_ok(st)) {   // last resort: k pairs for the thin kernel
+            lq_k = 1;
+            oa = orient(A);
+            lq_k = lq;
+        }
         // A small operand (at most 2^8 entries beside one of 2^16 or more, or
         // at most 1/1024 of the large one) is permuted into the ranked order
         // below rather than read as stored: its free labels then enter the
@@ -490,7 +509,10 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         // operand's permute is cheaper than the consumer's permute of the
         // larger result.  Failing that, the first choice stands.
         bool dropA = false, dropB = false;
-        for (int attempt = 0; attempt < 3; attempt++) {
+        // last resort for a thin consumer that reads this result as its A
+        bool relax = false;
+        const bool relax_ok = Z.consumer >= 0 && an.steps[Z.consumer].a == st.z && thin_ok(an.steps[Z.consumer]);
+        for (int attempt = 0; attempt < 4; attempt++) {
             keepA = oa >= 0 && !dropA;
             keepB = ob >= 0 && !dropB;
             beta_o.clear();
@@ -543,7 +565,9 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
                 int rlow = 5;
                 if (Z.consumer >= 0) {
                     int lgr = 0;
+                    if (relax) lq_k = 1;
                     rlow = inplace(zo, cg, lgr);
+                    lq_k = lq;
                     if (!rlow) return -1;
                 }
                 return std::min({wlow, rlow, 5}) - 0.25 * nsplit;
@@ -594,6 +618,11 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
                 if (dropA || dropB) continue;
             }
             if (attempt == 1 && best_s < 0) {
+                dropA = dropB = false;
+                continue;
+            }
+            if (best_s < 0 && !relax && relax_ok) {   // last resort: k pairs for a thin consumer
+                relax = true;
                 dropA = dropB = false;
                 continue;
             }

@@ -216,7 +216,8 @@ def test_slice_path_meets_a_lower_cap():
 def test_stored_53_qubit_path_layouts_keep_permutes_low():
     """The planner reads two-run operand layouts in place and orders each result
     for its consumer (small operands and results' kept operands into the order
-    the consumers sum in): on the stored 53-qubit path at most 3e10 permute
+    the consumers sum in; one-bit reduced runs where a thin consumer could not
+    read it otherwise): on the stored 53-qubit path at most 2e10 permute
     bytes per slice remain (a plain [batch][free][contracted] layout for every
     operand would move about 3.75e11)."""
     import json
@@ -228,7 +229,7 @@ def test_stored_53_qubit_path_layouts_keep_permutes_low():
     info = T.tnc_plan_analyze(net, np.array(path["ssa"], np.int32), np.array(path["sliced"], np.int32),
                               path["open_qubits"], "f16_4m")
     assert info["max_rank"] == 33
-    assert info["permute_bytes_per_slice"] <= 3.0e10, info["permute_bytes_per_slice"]
+    assert info["permute_bytes_per_slice"] <= 2.0e10, info["permute_bytes_per_slice"]
     assert 2.3e14 < info["flops_per_slice"] < 2.6e14
     T.tnc_network_destroy(net)
 
