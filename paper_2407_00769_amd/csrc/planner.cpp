@@ -409,11 +409,6 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
         std::vector<int> sb = {(int)st.beta.size(), (int)st.n.size(), (int)st.k.size()};
         // smallest run (bits) that a 16-byte chunk needs
         const int lq = an.dt == Dtype::C64 ? 1 : 2;
-        // Can a stored order be read in place by a GEMM whose groups are `g`
-        // (0 batch, 1 free, 2 reduced)?  The batch labels must form the top
-        // block; below it the free and the reduced labels may each lie in at
-        // most two runs, and the lowest run must hold a whole chunk.  Returns
-        // the length of that lowest run (bits) and its group, or 0.
         // The thin matrix-core kernel reads A in 8-byte pairs of k, so where a
         // step is one it takes (N = 4..32, K = 2, 4 or 8..64, 64 rows or more)
         // a lowest reduced run of one bit will do.  That is a last resort:
@@ -428,6 +423,12 @@ Analysis analyze(const Network &net, int n_steps, const int32_t *ssa, int n_slic
             if (!(K == 2 || K == 4 || (K % 8 == 0 && K <= 64))) return false;
             return !(N == 32 && K > 16);
         };
+        // Can a stored order be read in place by a GEMM whose groups are `g`
+        // (0 batch, 1 free, 2 reduced)?  The batch labels must form the top
+        // block; below it the free and the reduced labels may each lie in at
+        // most two runs, and the lowest run must hold a whole chunk (lq_k bits
+        // when it is reduced).  Returns the length of that lowest run (bits)
+        // and its group, or 0.
         auto inplace = [&](const std::vector<int> &order, const std::vector<int> &g, int &low_group) -> int {
             const int r = (int)order.size();
             int pos = 0;
