@@ -297,3 +297,22 @@ def test_sparse_work_is_smaller_on_a_path_searched_with_open_outputs():
     assert work(ssa1, sl1) < work(ssa0, sl0) / 3
     T.tnc_network_destroy(net)
 
+
+
+def test_30_qubit_path_layouts_keep_permutes_low():
+    """The 30-qubit block's path (5x6 grid, 14 cycles, 8 sliced labels, as the
+    benchmark finds it): the planner's ordering rules, the thin-consumer one
+    included, leave at most 8e7 permute bytes per slice (1.08e8 without the
+    thin-consumer rule)."""
+    c = workloads.config_circuit(2)
+    st = workloads.tn_structure(c)
+    r, l, d, o = cn.network_arrays(c, st)
+    net = T.tnc_network_create(r, l, d, c.n_qubits, o)
+    open_q = list(range(20, 30))
+    for seed in range(1, 20):
+        ssa, sl, _ = T.tnc_search(net, len(r), open_q, 22, restarts=64, seed=seed)
+        if len(sl) == 8:
+            break
+    info = T.tnc_plan_analyze(net, ssa, sl, open_q, "f16_4m")
+    assert info["permute_bytes_per_slice"] <= 8.0e7, info["permute_bytes_per_slice"]
+    T.tnc_network_destroy(net)
